@@ -1,0 +1,293 @@
+"""Seeded synthetic inputs for the nested long-wave model.
+
+This module only *describes* inputs: grid layouts, bathymetry, source
+parameters and random states.  It contains none of the time-step arithmetic;
+both the HIP library (through its binding) and the CPU oracle consume what it
+returns.  The Kochi model of the paper (Sec. V-A, Table 1) is not available,
+so its shapes are reproduced with synthetic coastlines:
+
+* ``c1()``: one 256x256 level at 810 m, a shelf from 6000 m depth to 50 m of
+  land along x plus eight seeded 200 m shoals (sigma 10 km), a 2 m Gaussian
+  hump (sigma 20 km) in the centre, open sides, dt = 1 s, 1000 steps.
+* ``c2(scale)``: four levels at 810/270/90/30 m, 1200x1000, 900^2, 1500^2,
+  2400^2 cells (about 10 M), a seeded wavy coastline with land up to 30 m,
+  dt = 0.2 s, 3600 s (18,000 steps), a 3 m elliptic uplift of 100x50 km about
+  150 km offshore.  ``scale`` divides every cell count (and the length scales
+  of the coast) for test-sized versions.
+* ``c3(scale)``: five levels at 810/270/90/30/10 m with the cell counts of the
+  paper's Table 1 (1266x1590, 1305^2, 1494^2, 3141^2, 5604^2; 47.2 M cells),
+  the three finest about 40 % land, finest-level sea no deeper than 100 m,
+  dt = 0.2 s, 6 h (108,000 steps).
+* ``random_state``: per-level random water levels and fluxes with a wet/dry
+  mix (dry land, thin films below and above the dry threshold, both flux
+  signs), used to exercise every branch of one step.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+G = 9.81
+GAUSS, COS2_ELLIPSE = 0, 1
+BC_OPEN, BC_WALL = 0, 1
+
+
+@dataclasses.dataclass
+class Source:
+    xc: float
+    yc: float
+    a: float
+    b: float
+    theta: float
+    amp: float
+    shape: int
+
+    def astuple(self):
+        return (self.xc, self.yc, self.a, self.b, self.theta, self.amp, self.shape)
+
+
+@dataclasses.dataclass
+class Scenario:
+    name: str
+    levels: list          # dicts: nx, ny, parent, off_i, off_j, h (ny, nx) float64
+    dx0: float
+    dt: float
+    steps: int
+    bc: tuple = (BC_OPEN,) * 4
+    g: float = G
+    manning_n: float = 0.025
+    dry_eps: float = 0.01
+    x0: float = 0.0
+    y0: float = 0.0
+    source: Source | None = None
+
+    @property
+    def cells(self) -> int:
+        return int(sum(lv["nx"] * lv["ny"] for lv in self.levels))
+
+    def level_dx(self, k: int) -> float:
+        dx = self.dx0
+        depth = 0
+        p = self.levels[k]["parent"]
+        while p != -1:
+            depth += 1
+            p = self.levels[p]["parent"]
+        for _ in range(depth):
+            dx = dx / 3.0
+        return dx
+
+    def level_origin(self, k: int):
+        """South-west corner of level k in metres (root origin + offsets)."""
+        chain = []
+        q = k
+        while q != -1:
+            chain.append(q)
+            q = self.levels[q]["parent"]
+        chain.reverse()
+        ox, oy, dx = self.x0, self.y0, self.dx0
+        for q in chain[1:]:
+            ox = ox + self.levels[q]["off_i"] * dx
+            oy = oy + self.levels[q]["off_j"] * dx
+            dx = dx / 3.0
+        return ox, oy
+
+    def cell_centres(self, k: int):
+        lv = self.levels[k]
+        dx = self.level_dx(k)
+        ox, oy = self.level_origin(k)
+        x = ox + (np.arange(lv["nx"], dtype=np.float64) + 0.5) * dx
+        y = oy + (np.arange(lv["ny"], dtype=np.float64) + 0.5) * dx
+        return np.meshgrid(x, y)
+
+    def oracle_kwargs(self):
+        return dict(levels=self.levels, dx0=self.dx0, dt=self.dt, g=self.g, manning_n=self.manning_n,
+                    dry_eps=self.dry_eps, bc=self.bc, x0=self.x0, y0=self.y0)
+
+    def check_cfl(self):
+        """Eq. (4) of the paper per level: dx/dt >= sqrt(2 g h_max)."""
+        for k, lv in enumerate(self.levels):
+            hmax = float(np.max(lv["h"]))
+            lim = (self.level_dx(k) / self.dt) ** 2 / (2.0 * self.g)
+            assert hmax <= lim, f"{self.name}: level {k} depth {hmax:.1f} m exceeds CFL limit {lim:.1f} m"
+
+
+def _level(nx, ny, parent=-1, off_i=0, off_j=0, h=None):
+    return dict(nx=int(nx), ny=int(ny), parent=int(parent), off_i=int(off_i), off_j=int(off_j), h=h)
+
+
+# ---------------------------------------------------------------------------
+def c1(seed: int = 1) -> Scenario:
+    rng = np.random.default_rng(seed)
+    nx = ny = 256
+    dx = 810.0
+    L = nx * dx
+    sc = Scenario("c1-single-256", [_level(nx, ny)], dx0=dx, dt=1.0, steps=1000)
+    X, Y = sc.cell_centres(0)
+    h = 6000.0 - 6050.0 * X / L
+    for _ in range(8):
+        cx, cy = rng.uniform(0, L, size=2)
+        h = h - 200.0 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * 10e3 ** 2))
+    sc.levels[0]["h"] = np.ascontiguousarray(h)
+    sc.source = Source(L / 2, L / 2, 20e3, 20e3, 0.0, 2.0, GAUSS)
+    sc.check_cfl()
+    return sc
+
+
+# ---------------------------------------------------------------------------
+class _Coast:
+    """A wavy north-south coastline with land to the east.
+
+    x_c(y) = X0 + sum_k a_k sin(2 pi k y / Ly + phi_k); offshore distance
+    s = x_c(y) - x; sea depth a piecewise-linear profile in s through the
+    knots, plus 200 m / 10 km shoals in deep water; land rises with a slope
+    up to zmax."""
+
+    def __init__(self, rng, X0, Ly, wiggle, knots, zmax, slope, Lx, nbumps, scale):
+        self.X0, self.Ly = X0, Ly
+        self.a = [rng.uniform(0.0, wiggle / k) for k in range(1, 7)]
+        self.phi = [rng.uniform(0.0, 2 * math.pi) for _ in range(6)]
+        self.knots = knots
+        self.zmax, self.slope = zmax, slope
+        self.bumps = [(rng.uniform(0, max(1.0, X0 - knots[-2][0] / 2)), rng.uniform(0, Ly)) for _ in range(nbumps)]
+        self.bump_sigma = 10e3 / scale
+
+    def xc(self, y):
+        out = np.full_like(y, self.X0)
+        for k in range(6):
+            out = out + self.a[k] * np.sin(2 * math.pi * (k + 1) * y / self.Ly + self.phi[k])
+        return out
+
+    def depth(self, X, Y):
+        s = self.xc(Y) - X
+        ks = np.array([k[0] for k in self.knots])
+        hs = np.array([k[1] for k in self.knots])
+        sea = np.interp(s, ks, hs)
+        deep = sea > 500.0
+        if self.bumps:
+            bump = np.zeros_like(X)
+            for (bx, by) in self.bumps:
+                bump = bump + 200.0 * np.exp(-((X - bx) ** 2 + (Y - by) ** 2) / (2.0 * self.bump_sigma ** 2))
+            sea = np.where(deep, sea - np.minimum(bump, sea - 500.0), sea)
+        land = -np.minimum(self.zmax, self.slope * (-s))
+        return np.where(s > 0.0, sea, land)
+
+
+def _nest_chain(sc: Scenario, sizes, centre_xy, land_shift):
+    """Append levels of the given (nx, ny) sizes, each the child of the
+    previous one, centred on centre_xy shifted landward (east) by
+    land_shift[k] times the level's width."""
+    for k, (nx, ny) in enumerate(sizes, start=1):
+        p = k - 1
+        pdx = sc.level_dx(p)
+        pox, poy = sc.level_origin(p)
+        fw, fh = nx // 3, ny // 3
+        width = fw * pdx
+        cx = centre_xy[0] + land_shift[k] * width
+        cy = centre_xy[1]
+        off_i = int(round((cx - pox) / pdx - fw / 2))
+        off_j = int(round((cy - poy) / pdx - fh / 2))
+        pn = sc.levels[p]
+        off_i = max(3, min(off_i, pn["nx"] - 3 - fw))
+        off_j = max(3, min(off_j, pn["ny"] - 3 - fh))
+        sc.levels.append(_level(nx, ny, p, off_i, off_j))
+
+
+def _fill_depths(sc: Scenario, coast: _Coast):
+    for k, lv in enumerate(sc.levels):
+        X, Y = sc.cell_centres(k)
+        lv["h"] = np.ascontiguousarray(coast.depth(X, Y))
+
+
+def c2(scale: int = 1, seed: int = 2) -> Scenario:
+    s = int(scale)
+    assert 1200 % s == 0 and 1000 % s == 0 and (900 // s) % 3 == 0 and (1500 // s) % 3 == 0 \
+        and (2400 // s) % 3 == 0, "scale must keep every child size divisible by 3"
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 1200 // s, 1000 // s
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    X0 = 0.75 * Lx
+    f = 1.0 / s
+    coast = _Coast(rng, X0, Ly, wiggle=8e3 * f,
+                   knots=[(0.0, 0.0), (20e3 * f, 100.0), (60e3 * f, 1000.0), (200e3 * f, 5000.0), (1e9, 5000.0)],
+                   zmax=30.0, slope=30.0 / (6e3 * f), Lx=Lx, nbumps=6, scale=s)
+    sc = Scenario(f"c2-nested4{'' if s == 1 else f'-s{s}'}", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=18000)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    _nest_chain(sc, [(900 // s, 900 // s), (1500 // s, 1500 // s), (2400 // s, 2400 // s)], (cx, cy),
+                land_shift=[0.0, 0.0, 0.0, 0.0])
+    _fill_depths(sc, coast)
+    # 3 m elliptic uplift, 100 x 50 km, about 150 km offshore, long axis along the coast
+    sc.source = Source(cx - 150e3 * f, cy, 50e3 * f, 25e3 * f, 0.5 * math.pi, 3.0, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+def c3(scale: int = 1, seed: int = 3) -> Scenario:
+    s = int(scale)
+    sizes = [(1305, 1305), (1494, 1494), (3141, 3141), (5604, 5604)]
+    assert all((n // s) % 3 == 0 and n % s == 0 for n, _ in sizes) or s == 1, \
+        "scale must keep every child size divisible by 3"
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 1266 // s, 1590 // s
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    X0 = 0.72 * Lx
+    f = 1.0 / s
+    coast = _Coast(rng, X0, Ly, wiggle=5e3 * f,
+                   knots=[(0.0, 0.0), (45e3 * f, 100.0), (90e3 * f, 1000.0), (250e3 * f, 5000.0), (1e9, 5000.0)],
+                   zmax=30.0, slope=1.0 / 1000.0 * s, Lx=Lx, nbumps=6, scale=s)
+    sc = Scenario(f"c3-nested5{'' if s == 1 else f'-s{s}'}", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=108000)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    _nest_chain(sc, [(n // s, m // s) for n, m in sizes], (cx, cy), land_shift=[0.0, 0.0, -0.1, -0.1, -0.1])
+    _fill_depths(sc, coast)
+    sc.source = Source(cx - 150e3 * f, cy, 50e3 * f, 25e3 * f, 0.5 * math.pi, 3.0, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+# ---------------------------------------------------------------------------
+def small_nested(seed: int = 7, nlev: int = 3, base=(36, 30), child=(27, 27), dx0=810.0, dt=0.2,
+                 bc=(BC_OPEN,) * 4) -> Scenario:
+    """A small chain of nests over a random coast, for step-level tests.
+    base: root cells; child: cells of every child (divisible by 3)."""
+    rng = np.random.default_rng(seed)
+    nx0, ny0 = base
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.6 * Lx, Ly, wiggle=0.05 * Ly,
+                   knots=[(0.0, 0.0), (0.1 * Lx, 20.0), (0.4 * Lx, 200.0), (1e12, 200.0)],
+                   zmax=5.0, slope=5.0 / (0.05 * Lx), Lx=Lx, nbumps=0, scale=1)
+    sc = Scenario(f"small-nested{nlev}", [_level(nx0, ny0)], dx0=dx0, dt=dt, steps=0, bc=tuple(bc))
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    _nest_chain(sc, [child] * (nlev - 1), (cx, cy), land_shift=[0.0] * nlev)
+    _fill_depths(sc, coast)
+    sc.source = Source(cx - 0.3 * Lx, cy, 0.1 * Lx, 0.05 * Ly, 0.5 * math.pi, 1.0, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+def random_state(sc: Scenario, seed: int, flux: float = 5.0):
+    """Random (eta, M, N) per level exercising every branch of one step.
+
+    Sea cells: eta ~ U(-1, 1) (clipped to the ground); land cells: half dry
+    (eta = -h), half covered by a film of depth U(0, 0.05) m (below and above
+    the 0.01 m dry threshold).  Fluxes ~ U(-flux, flux) on every face,
+    including faces between dry cells."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for lv in sc.levels:
+        h = lv["h"]
+        ny, nx = h.shape
+        eta = rng.uniform(-1.0, 1.0, size=(ny, nx))
+        film = rng.uniform(0.0, 0.05, size=(ny, nx))
+        dry = rng.uniform(size=(ny, nx)) < 0.5
+        eta = np.where(h > 0, eta, np.where(dry, -h, -h + film))
+        eta = np.where(h + eta < 0, -h, eta)
+        M = rng.uniform(-flux, flux, size=(ny, nx + 1))
+        N = rng.uniform(-flux, flux, size=(ny + 1, nx))
+        out.append((np.ascontiguousarray(eta), np.ascontiguousarray(M), np.ascontiguousarray(N)))
+    return out
