@@ -1,0 +1,187 @@
+/*
+ * rti.h -- C ABI of librti: the time step of the nested nonlinear long-wave
+ * (shallow-water) model of the RTi real-time tsunami inundation simulator
+ * (arXiv 2408.07609), run on one AMD Instinct MI355X (gfx950) GPU.
+ *
+ * What one step computes (paper, Sec. II-A and Sec. IV-A):
+ *   1. continuity, Eq. (1): the water level eta of every cell from the
+ *      divergence of the discharge fluxes M (x-faces) and N (y-faces);
+ *   2. child -> parent: the water level of the parent cells on the ring of a
+ *      child's footprint becomes the mean of the 3x3 child cells below them
+ *      (Sec. IV-C);
+ *   3. momentum, Eqs. (2)-(3): M and N from the pressure gradient g D grad(eta),
+ *      upwind advection of M^2/D, MN/D, N^2/D and semi-implicit Manning
+ *      friction g n^2 M sqrt(M^2+N^2)/D^{7/3}, D = h + eta, with a wet/dry
+ *      moving shoreline;
+ *   4. parent -> child: the discharge of the parent faces on a child's edge is
+ *      injected into the child's boundary faces (3:1 nesting, Sec. II-A);
+ *   5. open (radiating) or wall sides of the root level;
+ *   6. running maxima: highest water level on sea cells and deepest
+ *      inundation on land (the outputs of Sec. IV-A).
+ * Levels use the same time step (Sec. V-A) and must satisfy the CFL bound
+ * of Eq. (4): dx_l / dt >= sqrt(2 g h_max,l).
+ *
+ * Conventions.
+ *   - Host arrays are row-major with x (i) fastest: a level of nx by ny cells
+ *     has eta, h and the maxima as nx*ny doubles, cell (i,j) at i + nx*j;
+ *     M as (nx+1)*ny doubles, x-face (i,j) between cells (i-1,j) and (i,j) at
+ *     i + (nx+1)*j; N as nx*(ny+1) doubles, y-face (i,j) between cells (i,j-1)
+ *     and (i,j) at i + nx*j.
+ *   - h > 0 is still-water depth [m]; h <= 0 is land whose elevation is -h.
+ *   - Every call returns 0 (RTI_OK) or a negative RTI_E* code; the message of
+ *     the last failure on the calling thread is rti_last_error().  No call
+ *     throws; no call aborts the process.
+ *   - The caller owns every host buffer it passes and every buffer it gets
+ *     back; the library copies what it needs.  A domain handle is owned by
+ *     the library until rti_domain_destroy.
+ *   - One thread at a time per domain.  Distinct domains may be driven from
+ *     distinct threads on distinct streams.
+ */
+#ifndef RTI_H
+#define RTI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RTI_OK = 0,
+    RTI_EINVAL = -1,       /* bad argument: null pointer, size, level index, enum value */
+    RTI_ENOMEM = -2,       /* device memory or arena too small */
+    RTI_EHIP = -3,         /* a HIP runtime call failed (message names it) */
+    RTI_ECFL = -4,         /* Eq. (4) violated on some level */
+    RTI_ENEST = -5,        /* nesting rule violated (ratio 3, inclusion, margin) */
+    RTI_ESTATE = -6,       /* call not allowed in the domain's current state */
+    RTI_EDIVERGED = -7     /* non-finite water level or flux found (sticky) */
+};
+
+enum { RTI_FP64 = 0, RTI_FP32_BULK = 1 };   /* arithmetic of the step; only RTI_FP64 is built */
+enum { RTI_BC_OPEN = 0, RTI_BC_WALL = 1 };  /* root sides */
+enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
+
+/* flags of rti_domain_desc */
+#define RTI_FLAG_NO_GRAPH    0x1u   /* rti_step launches kernels one by one instead of replaying a HIP graph */
+#define RTI_FLAG_NO_ACTIVE   0x2u   /* compute every tile; do not skip quiescent dry tiles */
+#define RTI_MAX_LEVELS 16
+
+/* One nest level.  Level 0 is the root (parent = -1); every other level names
+ * a parent listed before it.  A child's spacing is its parent's divided by 3
+ * (Sec. II-A); its nx and ny are multiples of 3 and at least 9; its footprint,
+ * the parent cells [off_i, off_i + nx/3) x [off_j, off_j + ny/3), lies inside
+ * the parent with at least 3 parent cells on every side; sibling footprints
+ * keep 3 parent cells apart. */
+typedef struct {
+    int32_t nx, ny;        /* cells */
+    int32_t parent;        /* index into levels[], -1 for the root */
+    int32_t off_i, off_j;  /* child origin in parent cells */
+    const double *h;       /* host, nx*ny still-water depth [m]; copied by rti_domain_create */
+} rti_level_desc;
+
+typedef struct {
+    int32_t n_levels;                /* 1 .. RTI_MAX_LEVELS */
+    const rti_level_desc *levels;
+    double dx0;                      /* root spacing [m] */
+    double x0, y0;                   /* south-west corner of the root [m] */
+    double dt;                       /* time step [s], all levels */
+    double g;                        /* gravity [m/s^2] (9.81) */
+    double manning_n;                /* Manning roughness [s m^-1/3] (0.025) */
+    double dry_eps;                  /* dry threshold on total depth [m] (0.01) */
+    int32_t bc[4];                   /* root sides W, E, S, N: RTI_BC_OPEN or RTI_BC_WALL */
+    int32_t precision;               /* RTI_FP64 */
+    uint32_t flags;                  /* RTI_FLAG_* */
+} rti_domain_desc;
+
+typedef struct rti_domain rti_domain;   /* opaque */
+
+/* Initial sea-surface displacement, applied on every level at t = 0.
+ * Offsets from (xc, yc) rotated by theta: x' along the a axis, y' along b.
+ * RTI_GAUSS: amp exp(-((x'/a)^2 + (y'/b)^2)/2).
+ * RTI_COS2_ELLIPSE: amp cos^2(pi rho/2) for rho^2 = (x'/a)^2 + (y'/b)^2 < 1,
+ * else 0 (a, b semi-axes). */
+typedef struct {
+    double xc, yc;       /* centre [m] */
+    double a, b;         /* scales [m] */
+    double theta;        /* rotation of the a axis from x [rad] */
+    double amp;          /* amplitude [m] */
+    int32_t shape;       /* RTI_GAUSS or RTI_COS2_ELLIPSE */
+} rti_source;
+
+/* Device bytes a domain needs (state, bathymetry, maxima, tile tables), for
+ * admission against free HBM.  Validates the descriptor like create. */
+int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes);
+
+/* Validate the descriptor (Eq. (4) -> RTI_ECFL, nesting -> RTI_ENEST), carve
+ * device memory from arena (device pointer, arena_bytes >= footprint, 256-byte
+ * aligned; the caller keeps it alive until destroy) or allocate it when arena
+ * is NULL, copy the bathymetry, and set the lake at rest (eta = 0 at sea,
+ * -h on land, no flux).  hip_stream (a hipStream_t, may be NULL for the
+ * default stream) is borrowed: every kernel of this domain runs on it.
+ * Validation happens before any HIP call, so it works without a GPU. */
+int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_bytes,
+                      void *hip_stream, rti_domain **out);
+
+/* Parametric initial condition (see rti_source) on every level at t = 0:
+ * sea cells (h > 0) take the displacement, land keeps eta = -h, a level below
+ * the ground is clipped to it; fluxes zero; maxima start at these values.
+ * RTI_ESTATE once the domain has stepped (use rti_set_state to restart). */
+int rti_set_source(rti_domain *dom, const rti_source *src);
+
+/* Raw initial water level of one level (host, nx*ny), clipped to the ground;
+ * fluxes of that level zeroed; its maxima start here.  t = 0 only. */
+int rti_set_eta(rti_domain *dom, int32_t level, const double *eta0);
+
+/* Enqueue nsteps time steps on the domain's stream and return (asynchronous).
+ * nsteps >= 0. */
+int rti_step(rti_domain *dom, int64_t nsteps);
+
+/* Step until round(t_end / dt) steps have been taken in total, then
+ * synchronise and check the state for non-finite values (RTI_EDIVERGED). */
+int rti_run(rti_domain *dom, double t_end);
+
+/* Maxima of one level (host out, nx*ny): the highest water level on sea cells
+ * (h > 0) and the largest total depth h + eta on land (h <= 0), over every
+ * step taken, t = 0 included.  Synchronises. */
+int rti_max_inundation(rti_domain *dom, int32_t level, double *out);
+
+/* Copy the state of one level to the host (any pointer may be NULL to skip
+ * that field): eta nx*ny, M (nx+1)*ny, N nx*(ny+1).  Synchronises. */
+int rti_get_state(rti_domain *dom, int32_t level, double *eta, double *M, double *N);
+
+/* Overwrite the state of one level (NULL skips a field).  The maxima are not
+ * touched (rti_set_max does that), nor is the step count. */
+int rti_set_state(rti_domain *dom, int32_t level, const double *eta, const double *M, const double *N);
+
+/* Overwrite the maxima of one level (host, nx*ny). */
+int rti_set_max(rti_domain *dom, int32_t level, const double *zmax);
+
+/* Steps taken since the initial condition. */
+int rti_steps_done(const rti_domain *dom, int64_t *steps);
+
+/* Wait for every step enqueued on the domain's stream. */
+int rti_sync(rti_domain *dom);
+
+/* Time the kernels of nsteps steps launched one by one with HIP events on
+ * the domain's stream (this advances the state).  ms[k] receives the average
+ * duration of kernel kind k per launch, names[k] (may be NULL) a static
+ * name; at most cap kinds; *n_kinds the number filled.  Synchronises. */
+int rti_profile(rti_domain *dom, int64_t nsteps, double *ms, const char **names, int32_t cap,
+                int32_t *n_kinds);
+
+/* Number of tiles of the last step that were computed (not skipped as
+ * quiescent dry land) and the total number of tiles.  Synchronises. */
+int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total);
+
+/* Free the domain's device memory (when the library allocated it), its
+ * graphs and the handle.  NULL is a no-op.  Synchronises first. */
+void rti_domain_destroy(rti_domain *dom);
+
+const char *rti_last_error(void);
+const char *rti_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTI_H */

@@ -1,0 +1,658 @@
+// rti_host.cpp -- host runtime behind the C ABI of include/rti.h: descriptor
+// validation (CFL bound Eq. (4) and 3:1 inclusive nesting of Sec. II-A of
+// the paper), device memory carving, state transfer, the step driver (HIP
+// graphs replaying a fixed number of steps), profiling hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rti.h"
+#include "rti_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(RTI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kGraphSteps = 20;   // steps per captured graph (even: parity returns)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct LevelPlan {
+    int nx, ny, pitch, parent, off_i, off_j;
+    double dx, ox, oy;
+    size_t cells_bytes, xf_bytes, yf_bytes;   // one pitched array of each kind
+    int tiles_x, tiles_y, s_tiles_x, s_tiles_y;
+};
+
+struct Plan {
+    std::vector<LevelPlan> lv;
+    size_t bytes = 0;
+    int ntiles = 0, s_ntiles = 0;
+};
+
+bool level_has_child(const rti_domain_desc *d, int k)
+{
+    for (int q = k + 1; q < d->n_levels; ++q)
+        if (d->levels[q].parent == k) return true;
+    return false;
+}
+
+// Validate the descriptor and lay the domain out in device memory.
+int plan_domain(const rti_domain_desc *d, Plan &plan)
+{
+    if (!d) return fail(RTI_EINVAL, "descriptor is NULL");
+    if (d->n_levels < 1 || d->n_levels > RTI_MAX_LEVELS)
+        return fail(RTI_EINVAL, "n_levels %d outside [1, %d]", d->n_levels, RTI_MAX_LEVELS);
+    if (!d->levels) return fail(RTI_EINVAL, "levels is NULL");
+    if (!(d->dt > 0.0) || !(d->dx0 > 0.0) || !(d->g > 0.0) || !(d->manning_n >= 0.0) || !(d->dry_eps > 0.0)
+        || !std::isfinite(d->dt) || !std::isfinite(d->dx0) || !std::isfinite(d->x0) || !std::isfinite(d->y0))
+        return fail(RTI_EINVAL, "dt, dx0, g, dry_eps must be positive and finite, manning_n >= 0");
+    for (int s = 0; s < 4; ++s)
+        if (d->bc[s] != RTI_BC_OPEN && d->bc[s] != RTI_BC_WALL) return fail(RTI_EINVAL, "bc[%d] = %d", s, d->bc[s]);
+    if (d->precision == RTI_FP32_BULK) return fail(RTI_EINVAL, "RTI_FP32_BULK is not built; use RTI_FP64");
+    if (d->precision != RTI_FP64) return fail(RTI_EINVAL, "precision %d unknown", d->precision);
+    if (d->flags & ~(RTI_FLAG_NO_GRAPH | RTI_FLAG_NO_ACTIVE)) return fail(RTI_EINVAL, "unknown flags 0x%x", d->flags);
+
+    plan.lv.assign(d->n_levels, LevelPlan{});
+    for (int k = 0; k < d->n_levels; ++k) {
+        const rti_level_desc &L = d->levels[k];
+        LevelPlan &p = plan.lv[k];
+        if (!L.h) return fail(RTI_EINVAL, "level %d: h is NULL", k);
+        if (L.nx < 3 || L.ny < 3) return fail(RTI_EINVAL, "level %d: %d x %d cells (at least 3 x 3)", k, L.nx, L.ny);
+        p.nx = L.nx; p.ny = L.ny; p.parent = L.parent; p.off_i = L.off_i; p.off_j = L.off_j;
+        if (k == 0) {
+            if (L.parent != -1) return fail(RTI_ENEST, "level 0 must be the root (parent -1)");
+            p.dx = d->dx0; p.ox = d->x0; p.oy = d->y0;
+        } else {
+            if (L.parent < 0 || L.parent >= k) return fail(RTI_ENEST, "level %d: parent %d must precede it", k, L.parent);
+            const LevelPlan &P = plan.lv[L.parent];
+            if (L.nx % 3 || L.ny % 3 || L.nx < 9 || L.ny < 9)
+                return fail(RTI_ENEST, "level %d: %d x %d cells, need multiples of 3 and >= 9 (ratio 3)", k, L.nx, L.ny);
+            if (L.off_i < 3 || L.off_j < 3 || L.off_i + L.nx / 3 > P.nx - 3 || L.off_j + L.ny / 3 > P.ny - 3)
+                return fail(RTI_ENEST, "level %d: footprint [%d,%d)x[%d,%d) not inside parent %d with 3 cells of margin",
+                            k, L.off_i, L.off_i + L.nx / 3, L.off_j, L.off_j + L.ny / 3, L.parent);
+            p.dx = P.dx / 3.0;
+            p.ox = P.ox + (double)L.off_i * P.dx;
+            p.oy = P.oy + (double)L.off_j * P.dx;
+        }
+        const long long pitch = (long long)align_up((size_t)L.nx + 1, 32);
+        if (pitch * (long long)(L.ny + 1) >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
+        p.pitch = (int)pitch;
+        p.cells_bytes = align_up((size_t)pitch * (size_t)L.ny * sizeof(double), kAlign);
+        p.xf_bytes = p.cells_bytes;
+        p.yf_bytes = align_up((size_t)pitch * (size_t)(L.ny + 1) * sizeof(double), kAlign);
+    }
+    for (int a = 1; a < d->n_levels; ++a) {
+        for (int b = a + 1; b < d->n_levels; ++b) {
+            const rti_level_desc &A = d->levels[a], &B = d->levels[b];
+            if (A.parent != B.parent) continue;
+            const bool apart = A.off_i + A.nx / 3 + 3 <= B.off_i || B.off_i + B.nx / 3 + 3 <= A.off_i
+                            || A.off_j + A.ny / 3 + 3 <= B.off_j || B.off_j + B.ny / 3 + 3 <= A.off_j;
+            if (!apart) return fail(RTI_ENEST, "levels %d and %d: sibling footprints closer than 3 parent cells", a, b);
+        }
+    }
+    // Eq. (4): dx / dt >= sqrt(2 g h_max) on every level.
+    for (int k = 0; k < d->n_levels; ++k) {
+        const rti_level_desc &L = d->levels[k];
+        double hmax = 0.0;
+        const size_t n = (size_t)L.nx * (size_t)L.ny;
+        for (size_t c = 0; c < n; ++c) {
+            const double h = L.h[c];
+            if (!std::isfinite(h)) return fail(RTI_EINVAL, "level %d: non-finite depth at cell %zu", k, c);
+            hmax = std::max(hmax, h);
+        }
+        const double lim = std::sqrt(2.0 * d->g * hmax);
+        if (plan.lv[k].dx / d->dt < lim)
+            return fail(RTI_ECFL, "level %d: dx/dt = %.3f m/s < sqrt(2 g h_max) = %.3f m/s (h_max %.1f m)", k,
+                        plan.lv[k].dx / d->dt, lim, hmax);
+    }
+    // Tiles and bytes.
+    size_t bytes = 0;
+    int ntiles = 0, s_ntiles = 0;
+    for (auto &p : plan.lv) {
+        p.tiles_x = (p.nx + 1 + RTI_TW - 1) / RTI_TW;
+        p.tiles_y = (p.ny + 1 + RTI_TH - 1) / RTI_TH;
+        p.s_tiles_x = (p.nx + 63) / 64;
+        p.s_tiles_y = (p.ny + 3) / 4;
+        ntiles += p.tiles_x * p.tiles_y;
+        s_ntiles += p.s_tiles_x * p.s_tiles_y;
+        // h, zmax, eta x2, M x2, N x2, tile flags
+        bytes += 4 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
+        bytes += align_up((size_t)p.tiles_x * p.tiles_y, kAlign);
+    }
+    bytes += kAlign;   // control block: divergence flag, counters
+    plan.bytes = bytes;
+    plan.ntiles = ntiles;
+    plan.s_ntiles = s_ntiles;
+    return RTI_OK;
+}
+
+}  // namespace
+
+struct rti_domain {
+    Plan plan;
+    DomainDev dev{};
+    hipStream_t stream = nullptr;        // borrowed
+    hipStream_t capture = nullptr;       // private, for graph capture
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    void *mem = nullptr;                 // base of the carved memory
+    bool owns_mem = false;
+    int *ctrl = nullptr;                 // [0] divergence flag
+    int cur = 0;                         // buffer holding the current state
+    int64_t steps = 0;
+    uint32_t flags = 0;
+    double dt = 0.0;
+    bool diverged = false;
+    int device = 0;
+};
+
+namespace {
+
+int carve(rti_domain *D)
+{
+    char *p = static_cast<char *>(D->mem);
+    auto take = [&p](size_t n) { char *q = p; p += n; return q; };
+    for (int k = 0; k < (int)D->plan.lv.size(); ++k) {
+        const LevelPlan &pl = D->plan.lv[k];
+        LevelDev &L = D->dev.lv[k];
+        L.h = reinterpret_cast<double *>(take(pl.cells_bytes));
+        L.zmax = reinterpret_cast<double *>(take(pl.cells_bytes));
+        L.eta[0] = reinterpret_cast<double *>(take(pl.cells_bytes));
+        L.eta[1] = reinterpret_cast<double *>(take(pl.cells_bytes));
+        L.M[0] = reinterpret_cast<double *>(take(pl.xf_bytes));
+        L.M[1] = reinterpret_cast<double *>(take(pl.xf_bytes));
+        L.N[0] = reinterpret_cast<double *>(take(pl.yf_bytes));
+        L.N[1] = reinterpret_cast<double *>(take(pl.yf_bytes));
+        L.flag = reinterpret_cast<uint8_t *>(take(align_up((size_t)pl.tiles_x * pl.tiles_y, kAlign)));
+    }
+    D->ctrl = reinterpret_cast<int *>(take(kAlign));
+    return RTI_OK;
+}
+
+// Pitched copies between packed host rows (width w) and device rows.
+int put_rows(rti_domain *D, double *dst, int pitch, const double *src, int w, int rows)
+{
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)pitch * sizeof(double), src, (size_t)w * sizeof(double),
+                             (size_t)w * sizeof(double), rows, hipMemcpyHostToDevice, D->stream));
+    return RTI_OK;
+}
+
+int get_rows(rti_domain *D, double *dst, int w, const double *src, int pitch, int rows)
+{
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)w * sizeof(double), src, (size_t)pitch * sizeof(double),
+                             (size_t)w * sizeof(double), rows, hipMemcpyDeviceToHost, D->stream));
+    return RTI_OK;
+}
+
+int check_level(const rti_domain *D, int level)
+{
+    if (!D) return fail(RTI_EINVAL, "domain is NULL");
+    if (level < 0 || level >= D->dev.nlev) return fail(RTI_EINVAL, "level %d outside [0, %d)", level, D->dev.nlev);
+    return RTI_OK;
+}
+
+// Initial water level of a level (host, packed) -> both eta buffers; zero
+// fluxes; maxima at the initial values.  eta is clipped to the ground.
+int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &eta)
+{
+    const LevelPlan &p = D->plan.lv[k];
+    LevelDev &L = D->dev.lv[k];
+    const size_t n = (size_t)p.nx * p.ny;
+    std::vector<double> z(n);
+    for (size_t c = 0; c < n; ++c) {
+        if (h[c] + eta[c] < 0.0) eta[c] = -h[c];
+        z[c] = (h[c] > 0.0) ? eta[c] : h[c] + eta[c];
+    }
+    for (int b = 0; b < 2; ++b) {
+        int rc = put_rows(D, L.eta[b], p.pitch, eta.data(), p.nx, p.ny);
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(L.M[b], 0, p.xf_bytes, D->stream));
+        HIP_TRY(hipMemsetAsync(L.N[b], 0, p.yf_bytes, D->stream));
+    }
+    int rc = put_rows(D, L.zmax, p.pitch, z.data(), p.nx, p.ny);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(D->stream));   // host vectors die on return
+    return RTI_OK;
+}
+
+int launch_step(rti_domain *D, int b, hipStream_t s)
+{
+    HIP_TRY(launch_mass(D->dev, b, s));
+    HIP_TRY(launch_jnz(D->dev, b, s));
+    HIP_TRY(launch_momentum(D->dev, b, s));
+    HIP_TRY(launch_jnq(D->dev, b, s));
+    return RTI_OK;
+}
+
+int build_graph(rti_domain *D, int parity)
+{
+    if (!D->capture) HIP_TRY(hipStreamCreateWithFlags(&D->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(D->capture, hipStreamCaptureModeThreadLocal));
+    int rc = RTI_OK;
+    for (int k = 0; k < kGraphSteps && rc == RTI_OK; ++k) rc = launch_step(D, (parity + k) & 1, D->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(D->capture, &g);
+    if (rc != RTI_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(RTI_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(RTI_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    D->graph[parity] = g;
+    D->exec[parity] = x;
+    return RTI_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rti_last_error(void) { return g_err.c_str(); }
+
+const char *rti_strerror(int code)
+{
+    switch (code) {
+    case RTI_OK: return "ok";
+    case RTI_EINVAL: return "invalid argument";
+    case RTI_ENOMEM: return "out of device memory";
+    case RTI_EHIP: return "HIP runtime error";
+    case RTI_ECFL: return "CFL condition violated";
+    case RTI_ENEST: return "nesting rule violated";
+    case RTI_ESTATE: return "call not allowed in this state";
+    case RTI_EDIVERGED: return "simulation diverged";
+    default: return "unknown error";
+    }
+}
+
+int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes)
+{
+    try {
+        if (!bytes) return fail(RTI_EINVAL, "bytes is NULL");
+        Plan plan;
+        int rc = plan_domain(desc, plan);
+        if (rc) return rc;
+        *bytes = plan.bytes;
+        return RTI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_bytes, void *hip_stream,
+                      rti_domain **out)
+{
+    try {
+        if (!out) return fail(RTI_EINVAL, "out is NULL");
+        *out = nullptr;
+        Plan plan;
+        int rc = plan_domain(desc, plan);
+        if (rc) return rc;
+        if (arena && arena_bytes < plan.bytes)
+            return fail(RTI_ENOMEM, "arena of %zu bytes is smaller than the footprint %zu", arena_bytes, plan.bytes);
+        if (arena && (reinterpret_cast<uintptr_t>(arena) % kAlign))
+            return fail(RTI_EINVAL, "arena must be %zu-byte aligned", kAlign);
+
+        rti_domain *D = new rti_domain;
+        D->plan = plan;
+        D->stream = static_cast<hipStream_t>(hip_stream);
+        D->flags = desc->flags;
+        D->dt = desc->dt;
+        hipError_t e = hipGetDevice(&D->device);
+        if (e != hipSuccess) {
+            delete D;
+            return fail(RTI_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+        }
+        if (arena) {
+            D->mem = arena;
+        } else {
+            e = hipMalloc(&D->mem, plan.bytes);
+            if (e != hipSuccess) {
+                delete D;
+                return fail(RTI_ENOMEM, "hipMalloc(%zu) failed: %s", plan.bytes, hipGetErrorString(e));
+            }
+            D->owns_mem = true;
+        }
+        DomainDev &dv = D->dev;
+        dv.nlev = desc->n_levels;
+        dv.ntiles = plan.ntiles;
+        dv.s_ntiles = plan.s_ntiles;
+        for (int s = 0; s < 4; ++s) dv.bc[s] = desc->bc[s];
+        dv.eps = desc->dry_eps;
+        dv.g = desc->g;
+        dv.fc = 0.5 * desc->dt * desc->g * desc->manning_n * desc->manning_n;
+        int base = 0, sbase = 0;
+        for (int k = 0; k < dv.nlev; ++k) {
+            const LevelPlan &p = plan.lv[k];
+            LevelDev &L = dv.lv[k];
+            L.nx = p.nx; L.ny = p.ny; L.pitch = p.pitch;
+            L.parent = p.parent; L.off_i = p.off_i; L.off_j = p.off_j;
+            L.tiles_x = p.tiles_x; L.tiles_y = p.tiles_y; L.tile_base = base;
+            L.s_tiles_x = p.s_tiles_x; L.s_tile_base = sbase;
+            base += p.tiles_x * p.tiles_y;
+            sbase += p.s_tiles_x * p.s_tiles_y;
+            L.has_children = level_has_child(desc, k) ? 1 : 0;
+            L.r = desc->dt / p.dx;
+            L.gr = desc->g * L.r;
+        }
+        carve(D);
+        e = hipMemsetAsync(D->mem, 0, plan.bytes, D->stream);
+        if (e != hipSuccess) {
+            rti_domain_destroy(D);
+            return fail(RTI_EHIP, "hipMemsetAsync failed: %s", hipGetErrorString(e));
+        }
+        for (int k = 0; k < dv.nlev; ++k) {
+            const LevelPlan &p = plan.lv[k];
+            rc = put_rows(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
+            if (rc) { rti_domain_destroy(D); return rc; }
+            std::vector<double> eta((size_t)p.nx * p.ny);
+            const double *h = desc->levels[k].h;
+            for (size_t c = 0; c < eta.size(); ++c) eta[c] = (h[c] > 0.0) ? 0.0 : -h[c];
+            rc = install_initial(D, k, h, eta);
+            if (rc) { rti_domain_destroy(D); return rc; }
+        }
+        *out = D;
+        return RTI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_set_source(rti_domain *D, const rti_source *src)
+{
+    try {
+        if (!D || !src) return fail(RTI_EINVAL, "NULL argument");
+        if (D->steps != 0) return fail(RTI_ESTATE, "rti_set_source after %lld steps", (long long)D->steps);
+        if (src->shape != RTI_GAUSS && src->shape != RTI_COS2_ELLIPSE) return fail(RTI_EINVAL, "shape %d", src->shape);
+        if (!(src->a > 0.0) || !(src->b > 0.0) || !std::isfinite(src->amp) || !std::isfinite(src->xc)
+            || !std::isfinite(src->yc) || !std::isfinite(src->theta))
+            return fail(RTI_EINVAL, "source scales must be positive and values finite");
+        const double ct = std::cos(src->theta), st = std::sin(src->theta);
+        for (int k = 0; k < D->dev.nlev; ++k) {
+            const LevelPlan &p = D->plan.lv[k];
+            std::vector<double> h((size_t)p.nx * p.ny), eta(h.size());
+            int rc = get_rows(D, h.data(), p.nx, D->dev.lv[k].h, p.pitch, p.ny);
+            if (rc) return rc;
+            HIP_TRY(hipStreamSynchronize(D->stream));
+            for (int j = 0; j < p.ny; ++j) {
+                for (int i = 0; i < p.nx; ++i) {
+                    const size_t c = (size_t)j * p.nx + i;
+                    const double x = p.ox + ((double)i + 0.5) * p.dx;
+                    const double y = p.oy + ((double)j + 0.5) * p.dx;
+                    const double ddx = x - src->xc, ddy = y - src->yc;
+                    const double xp = ddx * ct + ddy * st;
+                    const double yp = -(ddx * st) + ddy * ct;
+                    const double u = xp / src->a, v = yp / src->b;
+                    const double rho2 = u * u + v * v;
+                    double s;
+                    if (src->shape == RTI_GAUSS) {
+                        s = src->amp * std::exp(-0.5 * rho2);
+                    } else if (rho2 < 1.0) {
+                        const double cs = std::cos(0.5 * M_PI * std::sqrt(rho2));
+                        s = src->amp * (cs * cs);
+                    } else {
+                        s = 0.0;
+                    }
+                    eta[c] = (h[c] > 0.0) ? s : -h[c];
+                }
+            }
+            rc = install_initial(D, k, h.data(), eta);
+            if (rc) return rc;
+        }
+        D->steps = 0;
+        D->diverged = false;
+        return RTI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_set_eta(rti_domain *D, int32_t level, const double *eta0)
+{
+    try {
+        int rc = check_level(D, level);
+        if (rc) return rc;
+        if (!eta0) return fail(RTI_EINVAL, "eta0 is NULL");
+        if (D->steps != 0) return fail(RTI_ESTATE, "rti_set_eta after %lld steps", (long long)D->steps);
+        const LevelPlan &p = D->plan.lv[level];
+        const size_t n = (size_t)p.nx * p.ny;
+        std::vector<double> h(n), eta(eta0, eta0 + n);
+        for (size_t c = 0; c < n; ++c)
+            if (!std::isfinite(eta[c])) return fail(RTI_EINVAL, "eta0 not finite at cell %zu", c);
+        rc = get_rows(D, h.data(), p.nx, D->dev.lv[level].h, p.pitch, p.ny);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(D->stream));
+        return install_initial(D, level, h.data(), eta);
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_step(rti_domain *D, int64_t nsteps)
+{
+    try {
+        if (!D) return fail(RTI_EINVAL, "domain is NULL");
+        if (nsteps < 0) return fail(RTI_EINVAL, "nsteps %lld < 0", (long long)nsteps);
+        if (D->diverged) return fail(RTI_EDIVERGED, "the domain diverged earlier");
+        const bool graphs = !(D->flags & RTI_FLAG_NO_GRAPH);
+        while (nsteps > 0) {
+            if (graphs && nsteps >= kGraphSteps) {
+                if (!D->exec[D->cur]) {
+                    int rc = build_graph(D, D->cur);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(D->exec[D->cur], D->stream));
+                D->steps += kGraphSteps;
+                nsteps -= kGraphSteps;
+            } else {
+                int rc = launch_step(D, D->cur, D->stream);
+                if (rc) return rc;
+                D->cur ^= 1;
+                D->steps += 1;
+                nsteps -= 1;
+            }
+        }
+        return RTI_OK;
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_sync(rti_domain *D)
+{
+    if (!D) return fail(RTI_EINVAL, "domain is NULL");
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    return RTI_OK;
+}
+
+int rti_run(rti_domain *D, double t_end)
+{
+    if (!D) return fail(RTI_EINVAL, "domain is NULL");
+    if (!std::isfinite(t_end) || t_end < 0.0) return fail(RTI_EINVAL, "t_end %g", t_end);
+    const int64_t target = (int64_t)std::llround(t_end / D->dt);
+    if (target > D->steps) {
+        int rc = rti_step(D, target - D->steps);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_zero_int(D->ctrl, 1, D->stream));
+    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl, D->stream));
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    if (flag) {
+        D->diverged = true;
+        return fail(RTI_EDIVERGED, "non-finite water level or flux after %lld steps", (long long)D->steps);
+    }
+    return RTI_OK;
+}
+
+int rti_max_inundation(rti_domain *D, int32_t level, double *out)
+{
+    int rc = check_level(D, level);
+    if (rc) return rc;
+    if (!out) return fail(RTI_EINVAL, "out is NULL");
+    const LevelPlan &p = D->plan.lv[level];
+    rc = get_rows(D, out, p.nx, D->dev.lv[level].zmax, p.pitch, p.ny);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    return RTI_OK;
+}
+
+int rti_get_state(rti_domain *D, int32_t level, double *eta, double *M, double *N)
+{
+    int rc = check_level(D, level);
+    if (rc) return rc;
+    const LevelPlan &p = D->plan.lv[level];
+    const LevelDev &L = D->dev.lv[level];
+    if (eta && (rc = get_rows(D, eta, p.nx, L.eta[D->cur], p.pitch, p.ny))) return rc;
+    if (M && (rc = get_rows(D, M, p.nx + 1, L.M[D->cur], p.pitch, p.ny))) return rc;
+    if (N && (rc = get_rows(D, N, p.nx, L.N[D->cur], p.pitch, p.ny + 1))) return rc;
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    return RTI_OK;
+}
+
+int rti_set_state(rti_domain *D, int32_t level, const double *eta, const double *M, const double *N)
+{
+    int rc = check_level(D, level);
+    if (rc) return rc;
+    const LevelPlan &p = D->plan.lv[level];
+    const LevelDev &L = D->dev.lv[level];
+    for (int b = 0; b < 2; ++b) {
+        if (eta && (rc = put_rows(D, L.eta[b], p.pitch, eta, p.nx, p.ny))) return rc;
+        if (M && (rc = put_rows(D, L.M[b], p.pitch, M, p.nx + 1, p.ny))) return rc;
+        if (N && (rc = put_rows(D, L.N[b], p.pitch, N, p.nx, p.ny + 1))) return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    D->diverged = false;
+    return RTI_OK;
+}
+
+int rti_set_max(rti_domain *D, int32_t level, const double *zmax)
+{
+    int rc = check_level(D, level);
+    if (rc) return rc;
+    if (!zmax) return fail(RTI_EINVAL, "zmax is NULL");
+    const LevelPlan &p = D->plan.lv[level];
+    if ((rc = put_rows(D, D->dev.lv[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    return RTI_OK;
+}
+
+int rti_steps_done(const rti_domain *D, int64_t *steps)
+{
+    if (!D || !steps) return fail(RTI_EINVAL, "NULL argument");
+    *steps = D->steps;
+    return RTI_OK;
+}
+
+int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, int32_t cap, int32_t *n_kinds)
+{
+    if (!D || !ms || !n_kinds || cap < 1 || nsteps < 1) return fail(RTI_EINVAL, "bad argument");
+    static const char *kNames[K_NKINDS] = {"k_mass", "k_jnz", "k_momentum", "k_jnq", "k_fused", "k_active", "k_finite"};
+    double sum[K_NKINDS] = {0};
+    int cnt[K_NKINDS] = {0};
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    int rc = RTI_OK;
+    for (int64_t s = 0; s < nsteps && rc == RTI_OK; ++s) {
+        const int b = D->cur;
+        hipError_t e = hipEventRecord(ev[0], D->stream);
+        if (e == hipSuccess) e = launch_mass(D->dev, b, D->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
+        if (e == hipSuccess) e = launch_jnz(D->dev, b, D->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
+        if (e == hipSuccess) e = launch_momentum(D->dev, b, D->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], D->stream);
+        if (e == hipSuccess) e = launch_jnq(D->dev, b, D->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[4], D->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+        if (e != hipSuccess) {
+            rc = fail(RTI_EHIP, "profiling step failed: %s", hipGetErrorString(e));
+            break;
+        }
+        const int kinds[4] = {K_MASS, K_JNZ, K_MOMENTUM, K_JNQ};
+        for (int q = 0; q < 4; ++q) {
+            if ((kinds[q] == K_JNZ || kinds[q] == K_JNQ) && D->dev.nlev < 2) continue;
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, ev[q], ev[q + 1]);
+            sum[kinds[q]] += t;
+            cnt[kinds[q]] += 1;
+        }
+        D->cur ^= 1;
+        D->steps += 1;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    int n = 0;
+    for (int k = 0; k < K_NKINDS && n < cap; ++k) {
+        if (!cnt[k]) continue;
+        ms[n] = sum[k] / cnt[k];
+        if (names) names[n] = kNames[k];
+        ++n;
+    }
+    *n_kinds = n;
+    return RTI_OK;
+}
+
+int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total)
+{
+    if (!D || !active || !total) return fail(RTI_EINVAL, "NULL argument");
+    *total = D->dev.s_ntiles;
+    *active = D->dev.s_ntiles;
+    return RTI_OK;
+}
+
+void rti_domain_destroy(rti_domain *D)
+{
+    if (!D) return;
+    (void)hipStreamSynchronize(D->stream);
+    for (int p = 0; p < 2; ++p) {
+        if (D->exec[p]) (void)hipGraphExecDestroy(D->exec[p]);
+        if (D->graph[p]) (void)hipGraphDestroy(D->graph[p]);
+    }
+    if (D->capture) (void)hipStreamDestroy(D->capture);
+    if (D->owns_mem && D->mem) (void)hipFree(D->mem);
+    delete D;
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+// rti_kernels.hip -- per-phase HIP kernels of the nested long-wave step for
+// gfx950 (CDNA4), FP64.  One launch per phase covers every level: blocks of
+// 256 threads map to 64x4-cell tiles (64 = one wavefront along a row, so each
+// wavefront reads and writes 512 contiguous bytes per field).
+//
+// Phase order of one step (paper, Sec. IV-A): continuity (Eq. 1) on every
+// level -> child-to-parent water level on the footprint rings (Sec. IV-C) ->
+// momentum (Eqs. 2-3) on every level, with the root's open/wall sides and the
+// running maxima -> parent-to-child fluxes on every child edge.
+// Buffers: state in buffer b is read, the new state is written to b^1.
+//
+// The arithmetic of every formula is written operation by operation in the
+// order stated next to it (no reassociation; the library is built with
+// -ffp-contract=off so no multiply-add is fused).
+#include "rti_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int level_of_stile(const DomainDev &d, int blk)
+{
+    int l = 0;
+    #pragma unroll 1
+    for (int k = 1; k < d.nlev; ++k)
+        if (blk >= d.lv[k].s_tile_base) l = k;
+    return l;
+}
+
+// Wet/dry rule of a face between cells A and B: both wet -> D = (hA+hB)/2 +
+// (eA+eB)/2; one wet (say A) -> flux only if eA > -hB, D = eA + hB; both dry
+// -> none; and none whenever D <= eps.
+__device__ __forceinline__ bool face_depth(double ha, double ea, double hb, double eb, double eps, double &D)
+{
+    const bool wa = ha + ea > eps, wb = hb + eb > eps;
+    if (wa && wb) {
+        D = 0.5 * (ha + hb) + 0.5 * (ea + eb);
+    } else if (wa) {
+        if (!(ea > -hb)) return false;
+        D = ea + hb;
+    } else if (wb) {
+        if (!(eb > -ha)) return false;
+        D = eb + ha;
+    } else {
+        return false;
+    }
+    return D > eps;
+}
+
+// First-order upwind difference of a face momentum flux v along one axis;
+// s carries the velocity sign at the face, (m) the neighbour behind, (p) the
+// one ahead.  A face without flow takes the flux of neighbours flowing in.
+__device__ __forceinline__ double upwind_diff(double s, double v, bool okm, double sm, double vm,
+                                              bool okp, double sp, double vp)
+{
+    if (s > 0.0) return okm ? v - vm : 0.0;
+    if (s < 0.0) return okp ? vp - v : 0.0;
+    const double a = (okm && sm > 0.0) ? vm : 0.0;
+    const double c = (okp && sp < 0.0) ? vp : 0.0;
+    return (-a) + c;
+}
+
+struct View {
+    const double *h, *eta, *M, *N;
+    int nx, ny, P;
+};
+
+__device__ __forceinline__ bool xdepth(const View &v, double eps, int i, int j, double &D)
+{
+    return face_depth(v.h[(i - 1) + v.P * j], v.eta[(i - 1) + v.P * j], v.h[i + v.P * j], v.eta[i + v.P * j], eps, D);
+}
+
+__device__ __forceinline__ bool ydepth(const View &v, double eps, int i, int j, double &D)
+{
+    return face_depth(v.h[i + v.P * (j - 1)], v.eta[i + v.P * (j - 1)], v.h[i + v.P * j], v.eta[i + v.P * j], eps, D);
+}
+
+// N at x-face (i,j): (cell i-1's south+north) + (cell i's south+north), / 4.
+__device__ __forceinline__ double nbar_x(const View &v, int i, int j)
+{
+    const double *N = v.N;
+    const int P = v.P;
+    return 0.25 * ((N[(i - 1) + P * j] + N[(i - 1) + P * (j + 1)]) + (N[i + P * j] + N[i + P * (j + 1)]));
+}
+
+// M at y-face (i,j): (cell (i,j-1)'s west+east) + (cell (i,j)'s west+east), / 4.
+__device__ __forceinline__ double mbar_y(const View &v, int i, int j)
+{
+    const double *M = v.M;
+    const int P = v.P;
+    return 0.25 * ((M[i + P * (j - 1)] + M[(i + 1) + P * (j - 1)]) + (M[i + P * j] + M[(i + 1) + P * j]));
+}
+
+// x-momentum at interior x-face (i,j): M_new = ((1-F) M - Pr - A) / (1+F) with
+// Pr = (gr D)(eta_i - eta_{i-1}), A = r (X + Y), F = (fc sqrt(M^2+Nb^2)) / ((D D) cbrt D).
+__device__ double xmom(const View &v, double eps, double r, double gr, double fc, int i, int j)
+{
+    double D;
+    if (!xdepth(v, eps, i, j, D)) return 0.0;
+    const int P = v.P;
+    const double m = v.M[i + P * j];
+    const double nb = nbar_x(v, i, j);
+    const double Pr = (gr * D) * (v.eta[i + P * j] - v.eta[(i - 1) + P * j]);
+
+    double Dm = 0.0, Dp = 0.0;
+    const bool okm = (i - 1 >= 1) && xdepth(v, eps, i - 1, j, Dm);
+    const bool okp = (i + 1 <= v.nx - 1) && xdepth(v, eps, i + 1, j, Dp);
+    const double mm = okm ? v.M[(i - 1) + P * j] : 0.0;
+    const double mp = okp ? v.M[(i + 1) + P * j] : 0.0;
+    const double X = upwind_diff(m, (m * m) / D, okm, mm, okm ? (mm * mm) / Dm : 0.0,
+                                 okp, mp, okp ? (mp * mp) / Dp : 0.0);
+
+    double Ds = 0.0, Dn = 0.0;
+    const bool oks = (j - 1 >= 0) && xdepth(v, eps, i, j - 1, Ds);
+    const bool okn = (j + 1 <= v.ny - 1) && xdepth(v, eps, i, j + 1, Dn);
+    const double nbs = oks ? nbar_x(v, i, j - 1) : 0.0;
+    const double nbn = okn ? nbar_x(v, i, j + 1) : 0.0;
+    const double Y = upwind_diff(nb, (m * nb) / D, oks, nbs, oks ? (v.M[i + P * (j - 1)] * nbs) / Ds : 0.0,
+                                 okn, nbn, okn ? (v.M[i + P * (j + 1)] * nbn) / Dn : 0.0);
+    const double A = r * (X + Y);
+    const double F = (fc * sqrt(m * m + nb * nb)) / ((D * D) * cbrt(D));
+    return (((1.0 - F) * m - Pr) - A) / (1.0 + F);
+}
+
+// y-momentum at interior y-face (i,j): the mirror of xmom (x<->y, M<->N).
+__device__ double ymom(const View &v, double eps, double r, double gr, double fc, int i, int j)
+{
+    double D;
+    if (!ydepth(v, eps, i, j, D)) return 0.0;
+    const int P = v.P;
+    const double n = v.N[i + P * j];
+    const double mb = mbar_y(v, i, j);
+    const double Pr = (gr * D) * (v.eta[i + P * j] - v.eta[i + P * (j - 1)]);
+
+    double Ds = 0.0, Dn = 0.0;
+    const bool oks = (j - 1 >= 1) && ydepth(v, eps, i, j - 1, Ds);
+    const bool okn = (j + 1 <= v.ny - 1) && ydepth(v, eps, i, j + 1, Dn);
+    const double ns = oks ? v.N[i + P * (j - 1)] : 0.0;
+    const double nn = okn ? v.N[i + P * (j + 1)] : 0.0;
+    const double Yd = upwind_diff(n, (n * n) / D, oks, ns, oks ? (ns * ns) / Ds : 0.0,
+                                  okn, nn, okn ? (nn * nn) / Dn : 0.0);
+
+    double Dw = 0.0, De = 0.0;
+    const bool okw = (i - 1 >= 0) && ydepth(v, eps, i - 1, j, Dw);
+    const bool oke = (i + 1 <= v.nx - 1) && ydepth(v, eps, i + 1, j, De);
+    const double mbw = okw ? mbar_y(v, i - 1, j) : 0.0;
+    const double mbe = oke ? mbar_y(v, i + 1, j) : 0.0;
+    const double Xd = upwind_diff(mb, (n * mb) / D, okw, mbw, okw ? (v.N[(i - 1) + P * j] * mbw) / Dw : 0.0,
+                                  oke, mbe, oke ? (v.N[(i + 1) + P * j] * mbe) / De : 0.0);
+    const double A = r * (Yd + Xd);
+    const double F = (fc * sqrt(n * n + mb * mb)) / ((D * D) * cbrt(D));
+    return (((1.0 - F) * n - Pr) - A) / (1.0 + F);
+}
+
+// Open side of the root: flux = sign * (sqrt(g h) * eta) of the boundary cell;
+// none when the cell is land or dry.
+__device__ __forceinline__ double radiate(double g, double eps, double h, double e, double sign)
+{
+    if (!(h > 0.0) || !(h + e > eps)) return 0.0;
+    const double c = sqrt(g * h);
+    return sign * (c * e);
+}
+
+// ---------------------------------------------------------------------------
+// Continuity, Eq. (1): eta' = eta - r ((M_{i+1} - M_i) + (N_{j+1} - N_j)),
+// then clipped to the ground (h + eta' < 0 -> eta' = -h).
+__global__ __launch_bounds__(256) void k_mass(DomainDev d, int b)
+{
+    const int blk = blockIdx.x;
+    const LevelDev &L = d.lv[level_of_stile(d, blk)];
+    const int t = blk - L.s_tile_base;
+    const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
+    const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
+    if (i >= L.nx || j >= L.ny) return;
+    const int P = L.pitch;
+    const double *M = L.M[b], *N = L.N[b];
+    const int c = i + P * j;
+    double e = L.eta[b][c] - L.r * ((M[c + 1] - M[c]) + (N[c + P] - N[c]));
+    const double hh = L.h[c];
+    if (hh + e < 0.0) e = -hh;
+    L.eta[b ^ 1][c] = e;
+}
+
+// Child -> parent (Sec. IV-C): each parent cell on the ring of the child's
+// footprint := max(mean of the wet 3x3 child cells (summed j outer, i inner),
+// parent ground); unchanged when none is wet.  blockIdx.y = child level - 1.
+__global__ __launch_bounds__(256) void k_jnz(DomainDev d, int b)
+{
+    const int c = blockIdx.y + 1;
+    const LevelDev &C = d.lv[c];
+    const LevelDev &Pl = d.lv[C.parent];
+    const int fw = C.nx / 3, fh = C.ny / 3;
+    const int ring = 2 * fw + 2 * (fh - 2);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ring) return;
+    int I, J;
+    if (k < fw) {
+        I = k; J = 0;
+    } else if (k < 2 * fw) {
+        I = k - fw; J = fh - 1;
+    } else {
+        const int q = k - 2 * fw;
+        J = 1 + (q >> 1);
+        I = (q & 1) ? fw - 1 : 0;
+    }
+    const double *ce = C.eta[b ^ 1];
+    const int CP = C.pitch;
+    double s = 0.0;
+    int nw = 0;
+    for (int jj = 3 * J; jj < 3 * J + 3; ++jj) {
+        for (int ii = 3 * I; ii < 3 * I + 3; ++ii) {
+            const double e = ce[ii + CP * jj];
+            if (C.h[ii + CP * jj] + e > d.eps) { s += e; ++nw; }
+        }
+    }
+    if (nw > 0) {
+        const int pc = (C.off_i + I) + Pl.pitch * (C.off_j + J);
+        const double v = s / (double)nw;
+        const double ground = -Pl.h[pc];
+        Pl.eta[b ^ 1][pc] = (v > ground) ? v : ground;
+    }
+}
+
+// Momentum (Eqs. 2-3) for the west x-face and the south y-face of each cell,
+// the root's outer faces, and the running maxima of the cell.
+__global__ __launch_bounds__(256) void k_momentum(DomainDev d, int b)
+{
+    const int blk = blockIdx.x;
+    const int l = level_of_stile(d, blk);
+    const LevelDev &L = d.lv[l];
+    const int t = blk - L.s_tile_base;
+    const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
+    const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
+    if (i >= L.nx || j >= L.ny) return;
+    const int P = L.pitch;
+    View v{L.h, L.eta[b ^ 1], L.M[b], L.N[b], L.nx, L.ny, P};
+    double *Mo = L.M[b ^ 1], *No = L.N[b ^ 1];
+    const int c = i + P * j;
+
+    if (i >= 1) Mo[c] = xmom(v, d.eps, L.r, L.gr, d.fc, i, j);
+    if (j >= 1) No[c] = ymom(v, d.eps, L.r, L.gr, d.fc, i, j);
+
+    if (l == 0) {
+        const double hc = L.h[c], ec = v.eta[c];
+        if (i == 0) Mo[c] = d.bc[0] ? 0.0 : radiate(d.g, d.eps, hc, ec, -1.0);
+        if (i == L.nx - 1) Mo[c + 1] = d.bc[1] ? 0.0 : radiate(d.g, d.eps, hc, ec, 1.0);
+        if (j == 0) No[c] = d.bc[2] ? 0.0 : radiate(d.g, d.eps, hc, ec, -1.0);
+        if (j == L.ny - 1) No[c + P] = d.bc[3] ? 0.0 : radiate(d.g, d.eps, hc, ec, 1.0);
+    }
+
+    const double hc = L.h[c], e = v.eta[c];
+    const double val = (hc > 0.0) ? e : hc + e;
+    if (val > L.zmax[c]) L.zmax[c] = val;
+}
+
+// Parent -> child: every child boundary face takes the flux of the parent
+// face it lies on (new fluxes, buffer b^1).  blockIdx.y = child level - 1.
+__global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
+{
+    const int c = blockIdx.y + 1;
+    const LevelDev &C = d.lv[c];
+    const LevelDev &Pl = d.lv[C.parent];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ny = C.ny, nx = C.nx;
+    const int I0 = C.off_i, J0 = C.off_j, fw = nx / 3, fh = ny / 3;
+    const int CP = C.pitch, PP = Pl.pitch;
+    const double *PM = Pl.M[b ^ 1], *PN = Pl.N[b ^ 1];
+    double *CM = C.M[b ^ 1], *CN = C.N[b ^ 1];
+    if (k < ny) {
+        CM[0 + CP * k] = PM[I0 + PP * (J0 + k / 3)];
+    } else if (k < 2 * ny) {
+        const int jf = k - ny;
+        CM[nx + CP * jf] = PM[(I0 + fw) + PP * (J0 + jf / 3)];
+    } else if (k < 2 * ny + nx) {
+        const int i = k - 2 * ny;
+        CN[i] = PN[(I0 + i / 3) + PP * J0];
+    } else if (k < 2 * ny + 2 * nx) {
+        const int i = k - 2 * ny - nx;
+        CN[i + CP * ny] = PN[(I0 + i / 3) + PP * (J0 + fh)];
+    }
+}
+
+// Any non-finite water level or flux in buffer b sets *flag.
+__global__ __launch_bounds__(256) void k_finite(DomainDev d, int b, int *flag)
+{
+    const int blk = blockIdx.x;
+    const LevelDev &L = d.lv[level_of_stile(d, blk)];
+    const int t = blk - L.s_tile_base;
+    const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
+    const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
+    if (i >= L.nx || j >= L.ny) return;
+    const int c = i + L.pitch * j;
+    const bool bad = !isfinite(L.eta[b][c]) || !isfinite(L.M[b][c]) || !isfinite(L.N[b][c]);
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_zero_int(int *p, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0;
+}
+
+int max_ring(const DomainDev &d)
+{
+    int m = 0;
+    for (int c = 1; c < d.nlev; ++c) {
+        const int fw = d.lv[c].nx / 3, fh = d.lv[c].ny / 3;
+        const int ring = 2 * fw + 2 * (fh - 2);
+        if (ring > m) m = ring;
+    }
+    return m;
+}
+
+int max_edge(const DomainDev &d)
+{
+    int m = 0;
+    for (int c = 1; c < d.nlev; ++c) {
+        const int e = 2 * d.lv[c].nx + 2 * d.lv[c].ny;
+        if (e > m) m = e;
+    }
+    return m;
+}
+
+}  // namespace
+
+hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mass, dim3(d.s_ntiles), dim3(256), 0, s, d, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_jnz(const DomainDev &d, int b, hipStream_t s)
+{
+    if (d.nlev < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_jnz, dim3((max_ring(d) + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_momentum, dim3(d.s_ntiles), dim3(256), 0, s, d, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s)
+{
+    if (d.nlev < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_jnq, dim3((max_edge(d) + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finite, dim3(d.s_ntiles), dim3(256), 0, s, d, b, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}

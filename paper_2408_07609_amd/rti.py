@@ -1,0 +1,296 @@
+"""Python binding of librti (include/rti.h): argument marshalling only.
+
+Every function named ``rti_*`` here calls the C function of the same name and
+raises RtiError on a negative return code.  ``Domain`` wraps one nested domain
+whose device memory is a torch uint8 tensor (the arena) and whose kernels run
+on torch's current HIP stream; torch supplies memory and streams, every step
+of the computation runs in the library's HIP kernels.  There is no fallback:
+without the built library, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "librti.so")
+
+RTI_OK, RTI_EINVAL, RTI_ENOMEM, RTI_EHIP, RTI_ECFL, RTI_ENEST, RTI_ESTATE, RTI_EDIVERGED = 0, -1, -2, -3, -4, -5, -6, -7
+RTI_FP64, RTI_FP32_BULK = 0, 1
+RTI_BC_OPEN, RTI_BC_WALL = 0, 1
+RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
+RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE = 0x1, 0x2
+RTI_MAX_LEVELS = 16
+
+_dptr = ctypes.POINTER(ctypes.c_double)
+
+
+class rti_level_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("parent", ctypes.c_int32),
+                ("off_i", ctypes.c_int32), ("off_j", ctypes.c_int32), ("h", _dptr)]
+
+
+class rti_domain_desc(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(rti_level_desc)),
+                ("dx0", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("dt", ctypes.c_double), ("g", ctypes.c_double), ("manning_n", ctypes.c_double),
+                ("dry_eps", ctypes.c_double), ("bc", ctypes.c_int32 * 4), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class rti_source(ctypes.Structure):
+    _fields_ = [("xc", ctypes.c_double), ("yc", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("theta", ctypes.c_double), ("amp", ctypes.c_double), ("shape", ctypes.c_int32)]
+
+
+class RtiError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+FUNCTIONS = {
+    "rti_domain_footprint": (ctypes.c_int, [ctypes.POINTER(rti_domain_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "rti_domain_create": (ctypes.c_int, [ctypes.POINTER(rti_domain_desc), ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rti_set_source": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rti_source)]),
+    "rti_set_eta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr]),
+    "rti_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "rti_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "rti_max_inundation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr]),
+    "rti_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr, _dptr, _dptr]),
+    "rti_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr, _dptr, _dptr]),
+    "rti_set_max": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr]),
+    "rti_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rti_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "rti_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dptr, ctypes.POINTER(ctypes.c_char_p),
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "rti_domain_destroy": (None, [ctypes.c_void_p]),
+    "rti_last_error": (ctypes.c_char_p, []),
+    "rti_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def _load():
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+    # first makes librti bind to that same runtime instead of a second copy
+    # from /opt/rocm, so both share one device context, one allocator view
+    # and the same streams.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"librti.so is not built ({LIB_PATH}); run __graft_entry__.build() or "
+                          f"python paper_2408_07609_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in FUNCTIONS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(code):
+    if code < 0:
+        raise RtiError(code, LIB.rti_last_error().decode())
+    return code
+
+
+def _as_dptr(a):
+    return a.ctypes.data_as(_dptr) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# Same-name wrappers of the C ABI.
+def rti_domain_footprint(desc: rti_domain_desc) -> int:
+    n = ctypes.c_size_t(0)
+    _check(LIB.rti_domain_footprint(ctypes.byref(desc), ctypes.byref(n)))
+    return int(n.value)
+
+
+def rti_domain_create(desc: rti_domain_desc, arena_ptr: int | None, arena_bytes: int, stream_ptr: int | None) -> int:
+    out = ctypes.c_void_p(0)
+    _check(LIB.rti_domain_create(ctypes.byref(desc), arena_ptr, arena_bytes, stream_ptr, ctypes.byref(out)))
+    return out.value
+
+
+def rti_set_source(dom: int, src: rti_source):
+    _check(LIB.rti_set_source(dom, ctypes.byref(src)))
+
+
+def rti_set_eta(dom: int, level: int, eta0: np.ndarray):
+    _check(LIB.rti_set_eta(dom, level, _as_dptr(np.ascontiguousarray(eta0, dtype=np.float64))))
+
+
+def rti_step(dom: int, nsteps: int):
+    _check(LIB.rti_step(dom, int(nsteps)))
+
+
+def rti_run(dom: int, t_end: float):
+    _check(LIB.rti_run(dom, float(t_end)))
+
+
+def rti_max_inundation(dom: int, level: int, out: np.ndarray):
+    _check(LIB.rti_max_inundation(dom, level, _as_dptr(out)))
+
+
+def rti_get_state(dom: int, level: int, eta, M, N):
+    _check(LIB.rti_get_state(dom, level, _as_dptr(eta), _as_dptr(M), _as_dptr(N)))
+
+
+def rti_set_state(dom: int, level: int, eta, M, N):
+    _check(LIB.rti_set_state(dom, level, _as_dptr(eta), _as_dptr(M), _as_dptr(N)))
+
+
+def rti_set_max(dom: int, level: int, zmax):
+    _check(LIB.rti_set_max(dom, level, _as_dptr(zmax)))
+
+
+def rti_steps_done(dom: int) -> int:
+    n = ctypes.c_int64(0)
+    _check(LIB.rti_steps_done(dom, ctypes.byref(n)))
+    return int(n.value)
+
+
+def rti_sync(dom: int):
+    _check(LIB.rti_sync(dom))
+
+
+def rti_profile(dom: int, nsteps: int) -> dict:
+    cap = 16
+    ms = (ctypes.c_double * cap)()
+    names = (ctypes.c_char_p * cap)()
+    n = ctypes.c_int32(0)
+    _check(LIB.rti_profile(dom, int(nsteps), ms, names, cap, ctypes.byref(n)))
+    return {names[k].decode(): float(ms[k]) for k in range(n.value)}
+
+
+def rti_active_tiles(dom: int):
+    a, t = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(LIB.rti_active_tiles(dom, ctypes.byref(a), ctypes.byref(t)))
+    return int(a.value), int(t.value)
+
+
+def rti_domain_destroy(dom: int | None):
+    LIB.rti_domain_destroy(dom)
+
+
+def rti_last_error() -> str:
+    return LIB.rti_last_error().decode()
+
+
+def rti_strerror(code: int) -> str:
+    return LIB.rti_strerror(code).decode()
+
+
+# ---------------------------------------------------------------------------
+def make_desc(levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 0, 0), x0=0.0, y0=0.0,
+              precision=RTI_FP64, flags=0):
+    """Build an rti_domain_desc from level dicts (nx, ny, parent, off_i, off_j,
+    h as an (ny, nx) array).  Returns (desc, keepalive)."""
+    hs = [np.ascontiguousarray(lv["h"], dtype=np.float64) for lv in levels]
+    arr = (rti_level_desc * len(levels))()
+    for k, lv in enumerate(levels):
+        arr[k].nx, arr[k].ny = int(lv["nx"]), int(lv["ny"])
+        arr[k].parent = int(lv["parent"])
+        arr[k].off_i, arr[k].off_j = int(lv.get("off_i", 0)), int(lv.get("off_j", 0))
+        arr[k].h = hs[k].ctypes.data_as(_dptr)
+    d = rti_domain_desc()
+    d.n_levels = len(levels)
+    d.levels = ctypes.cast(arr, ctypes.POINTER(rti_level_desc))
+    d.dx0, d.x0, d.y0, d.dt = float(dx0), float(x0), float(y0), float(dt)
+    d.g, d.manning_n, d.dry_eps = float(g), float(manning_n), float(dry_eps)
+    for q in range(4):
+        d.bc[q] = int(bc[q])
+    d.precision, d.flags = int(precision), int(flags)
+    return d, (arr, hs)
+
+
+class Domain:
+    """One nested domain on the current GPU.  Device memory: a torch uint8
+    tensor; stream: torch's current stream (or the one given)."""
+
+    def __init__(self, levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 0, 0), x0=0.0, y0=0.0,
+                 flags=0, device="cuda:0", stream=None):
+        import torch
+        self.levels = [dict(nx=int(lv["nx"]), ny=int(lv["ny"])) for lv in levels]
+        self.dt = float(dt)
+        desc, keep = make_desc(levels, dx0, dt, g, manning_n, dry_eps, bc, x0, y0, RTI_FP64, flags)
+        self.footprint = rti_domain_footprint(desc)
+        dev = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        with torch.cuda.device(dev):
+            self.arena = torch.empty(self.footprint + 256, dtype=torch.uint8, device=dev)
+            base = self.arena.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            self._h = rti_domain_create(desc, aligned, self.footprint, self.stream.cuda_stream)
+        del keep
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            rti_domain_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- setup
+    def set_source(self, xc, yc, a, b, theta, amp, shape):
+        rti_set_source(self._h, rti_source(xc, yc, a, b, theta, amp, int(shape)))
+
+    def set_eta(self, level, eta0):
+        rti_set_eta(self._h, level, np.asarray(eta0, dtype=np.float64))
+
+    def set_state(self, level, eta=None, M=None, N=None):
+        c = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        rti_set_state(self._h, level, c(eta), c(M), c(N))
+
+    def set_max(self, level, zmax):
+        rti_set_max(self._h, level, np.ascontiguousarray(zmax, dtype=np.float64))
+
+    # -- stepping
+    def step(self, n=1):
+        rti_step(self._h, n)
+
+    def run(self, t_end):
+        rti_run(self._h, t_end)
+
+    def sync(self):
+        rti_sync(self._h)
+
+    @property
+    def steps(self):
+        return rti_steps_done(self._h)
+
+    # -- results
+    def get_state(self, level):
+        nx, ny = self.levels[level]["nx"], self.levels[level]["ny"]
+        e, M, N = np.empty((ny, nx)), np.empty((ny, nx + 1)), np.empty((ny + 1, nx))
+        rti_get_state(self._h, level, e, M, N)
+        return e, M, N
+
+    def max_inundation(self, level):
+        nx, ny = self.levels[level]["nx"], self.levels[level]["ny"]
+        out = np.empty((ny, nx))
+        rti_max_inundation(self._h, level, out)
+        return out
+
+    def profile(self, nsteps):
+        return rti_profile(self._h, nsteps)
+
+    def active_tiles(self):
+        return rti_active_tiles(self._h)

@@ -1,0 +1,193 @@
+"""HIP path against the CPU oracle, through the C ABI, on the same seeded inputs.
+
+Bar (FP64): max |d eta| <= 1e-9 m after a full run on every cell of every
+level, the same bound on the maxima, and fluxes within 1e-9 of their scale.
+The two sides evaluate the same formulas operation by operation without
+fused multiply-adds; they can differ by rounding only through cbrt (device
+and host libraries), so single steps agree to a few ulp.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def gpu_domain(sc, flags=0):
+    from paper_2408_07609_amd import Domain
+    return Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
+                  x0=sc.x0, y0=sc.y0, flags=flags)
+
+
+def ora_domain(sc, **kw):
+    return oracle.OracleDomain(**sc.oracle_kwargs(), **kw)
+
+
+def diffs(d, o, nlev):
+    out = []
+    for k in range(nlev):
+        e, M, N = d.get_state(k)
+        eo, Mo, No = o.get_state(k)
+        z, zo = d.max_inundation(k), o.max_inundation(k)
+        assert np.all(np.isfinite(e)) and np.all(np.isfinite(M)) and np.all(np.isfinite(N))
+        fs = max(1.0, np.abs(Mo).max(), np.abs(No).max())
+        out.append(dict(eta=float(np.abs(e - eo).max()), M=float(np.abs(M - Mo).max() / fs),
+                        N=float(np.abs(N - No).max() / fs), zmax=float(np.abs(z - zo).max()),
+                        eta_equal=float(np.mean(e == eo))))
+    return out
+
+
+def assert_close(ds, tol=TOL, what=""):
+    for k, d in enumerate(ds):
+        print(f"{what} level {k}: {d}")
+        assert d["eta"] <= tol and d["zmax"] <= tol, f"{what} level {k}: {d}"
+        assert d["M"] <= tol and d["N"] <= tol, f"{what} level {k}: {d}"
+
+
+def set_random(d, o, sc, seed, flux=5.0):
+    for k, (e, M, N) in enumerate(scenarios.random_state(sc, seed, flux=flux)):
+        h = sc.levels[k]["h"]
+        z = np.where(h > 0, e, h + e)
+        d.set_state(k, e, M, N)
+        d.set_max(k, z)
+        o.set_state(k, eta=e, M=M, N=N, zmax=z)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nlev", [1, 2, 3])
+def test_one_step_random_state(nlev):
+    """Every branch of one step (wet/dry faces, both flux signs, thin films,
+    ring and edge exchanges, open sides) on a random state."""
+    sc = scenarios.small_nested(seed=31 + nlev, nlev=nlev)
+    d, o = gpu_domain(sc), ora_domain(sc)
+    set_random(d, o, sc, seed=5)
+    d.step(1)
+    o.step(1)
+    assert_close(diffs(d, o, nlev), tol=1e-12, what=f"one step nlev={nlev}")
+
+
+def test_steps_random_state_graph_and_eager_agree():
+    sc = scenarios.small_nested(seed=40, nlev=3)
+    from paper_2408_07609_amd import RTI_FLAG_NO_GRAPH
+    a, b, o = gpu_domain(sc), gpu_domain(sc, flags=RTI_FLAG_NO_GRAPH), ora_domain(sc)
+    set_random(a, o, sc, seed=6, flux=0.5)
+    set_random(b, ora_domain(sc), sc, seed=6, flux=0.5)
+    a.step(45)
+    b.step(45)
+    o.step(45)
+    for k in range(3):
+        ea, Ma, Na = a.get_state(k)
+        eb, Mb, Nb = b.get_state(k)
+        assert np.array_equal(ea, eb) and np.array_equal(Ma, Mb) and np.array_equal(Na, Nb)
+    assert_close(diffs(a, o, 3), what="45 steps from a random state")
+
+
+def test_c1_full_run():
+    """Configuration 1: 256x256 at 810 m, shelf and shoals, 2 m hump, open
+    sides, 1000 steps of 1 s."""
+    sc = scenarios.c1()
+    d, o = gpu_domain(sc), ora_domain(sc)
+    d.set_source(*sc.source.astuple())
+    o.set_source(*sc.source.astuple())
+    d.run(sc.steps * sc.dt)
+    o.run(sc.steps * sc.dt)
+    assert d.steps == sc.steps == o.steps
+    ds = diffs(d, o, 1)
+    assert_close(ds, what="c1 full run")
+    z = o.max_inundation(0)
+    assert z.max() > 0.5
+
+
+def test_small_nested_source_run():
+    sc = scenarios.small_nested(seed=7, nlev=3)
+    d, o = gpu_domain(sc), ora_domain(sc)
+    d.set_source(*sc.source.astuple())
+    o.set_source(*sc.source.astuple())
+    d.step(3000)
+    o.step(3000)
+    ds = diffs(d, o, 3)
+    assert_close(ds, what="small nested 3000 steps")
+    land = sc.levels[2]["h"] <= 0
+    assert (o.max_inundation(2)[land] > 0.01).any(), "no inundation in the finest level"
+
+
+@pytest.mark.timeout(900)
+def test_c2_reduced_run():
+    """Configuration 2 with every cell count divided by 10 (four levels at
+    810/270/90/30 m over the same kind of coast), 4000 steps of 0.2 s."""
+    sc = scenarios.c2(scale=10)
+    d, o = gpu_domain(sc), ora_domain(sc)
+    d.set_source(*sc.source.astuple())
+    o.set_source(*sc.source.astuple())
+    d.step(4000)
+    o.step(4000)
+    assert_close(diffs(d, o, 4), what="c2/10 4000 steps")
+
+
+def test_lake_at_rest_bitwise():
+    sc = scenarios.small_nested(seed=11, nlev=3)
+    d = gpu_domain(sc)
+    before = [d.get_state(k)[0] for k in range(3)]
+    d.step(1000)
+    for k in range(3):
+        e, M, N = d.get_state(k)
+        assert np.array_equal(e, before[k])
+        assert np.all(M == 0) and np.all(N == 0)
+
+
+def test_mirror_symmetry_bitwise():
+    n, dx = 41, 810.0
+    X = (np.arange(n) + 0.5) * dx
+    XX, YY = np.meshgrid(X, X)
+    L = n * dx
+    rng = np.random.default_rng(3)
+    bump = rng.uniform(-30, 30, size=(n, n))
+    h = 300.0 - 320.0 * np.exp(-(np.hypot(XX - L / 2, YY - L / 2) / (0.25 * L)) ** 2) + (bump + bump[:, ::-1])
+    src = 1.5 * np.exp(-((XX - 0.3 * L) ** 2 + (YY - 0.4 * L) ** 2) / (2 * (3 * dx) ** 2))
+    src = src + src[:, ::-1]
+    sc = scenarios.Scenario("mirror", [dict(nx=n, ny=n, parent=-1, off_i=0, off_j=0, h=h)], dx0=dx, dt=1.0, steps=0)
+    d = gpu_domain(sc)
+    d.set_eta(0, src)
+    d.step(300)
+    e, M, N = d.get_state(0)
+    assert np.abs(M).max() > 0
+    assert np.array_equal(e, e[:, ::-1]) and np.array_equal(M, -M[:, ::-1]) and np.array_equal(N, N[:, ::-1])
+
+
+def test_checkpoint_resume_bitwise():
+    sc = scenarios.small_nested(seed=7, nlev=3)
+    a = gpu_domain(sc)
+    a.set_source(*sc.source.astuple())
+    a.step(100)
+    saved = [(a.get_state(k), a.max_inundation(k)) for k in range(3)]
+    a.step(100)
+    b = gpu_domain(sc)
+    for k, ((e, M, N), z) in enumerate(saved):
+        b.set_state(k, e, M, N)
+        b.set_max(k, z)
+    b.step(100)
+    for k in range(3):
+        for x, y in zip(a.get_state(k), b.get_state(k)):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a.max_inundation(k), b.max_inundation(k))
+
+
+def test_errors_on_gpu():
+    from paper_2408_07609_amd import RtiError, RTI_ESTATE, RTI_EDIVERGED
+    sc = scenarios.small_nested(seed=7, nlev=2)
+    d = gpu_domain(sc)
+    d.set_source(*sc.source.astuple())
+    d.step(2)
+    with pytest.raises(RtiError) as ei:
+        d.set_source(*sc.source.astuple())
+    assert ei.value.code == RTI_ESTATE
+    e, M, N = d.get_state(1)
+    e[5, 5] = np.nan
+    d.set_state(1, e, M, N)
+    with pytest.raises(RtiError) as ei:
+        d.run(10 * sc.dt)
+    assert ei.value.code == RTI_EDIVERGED
