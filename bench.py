@@ -28,6 +28,8 @@ BYTES_PER_CELL = {
     "k_momentum": 8 * (5 + 3),      # eta, h, M, N, max in; M, N, max out
     "k_fused": 8 * (4 + 3 + 2),     # eta, M, N, h in; eta, M, N out; max in+out
 }
+# FP32-bulk: eta in and out FP64 (16 B); M, N, h in and M, N out FP32 (20 B); max in+out FP32 (8 B)
+BYTES_PER_CELL_FP32_BULK = {"k_fused": 16 + 20 + 8}
 
 
 def log(msg):
@@ -36,24 +38,44 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for p in ("paper_2408_07609_amd/csrc/rti_kernels.hip", "paper_2408_07609_amd/csrc/rti_internal.h"):
+    for p in ("paper_2408_07609_amd/csrc/rti_kernels.hip", "paper_2408_07609_amd/csrc/rti_fused.hip",
+              "paper_2408_07609_amd/csrc/rti_device.h", "paper_2408_07609_amd/csrc/rti_internal.h"):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, cells):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+def measured_traffic(kernel, workload, cells_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/traffic.json, written by bench_traffic.py): the measured bytes
+    per computed cell of this kernel on this workload, times the cells one
+    launch computes here.  None when the counters were taken on another
+    kernel source or workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel)
-    if not e or e.get("source_hash") != source_hash() or e.get("cells") != cells:
+    if not e or e.get("source_hash") != source_hash() or e.get("workload") != workload:
         return None
-    return e["bytes_per_launch"]
+    return e["bytes_per_cell"] * cells_per_launch
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def copy_probe():
+    """A plain 1 GiB device-to-device copy by torch's copy kernel: rocprofv3's
+    FETCH_SIZE / WRITE_SIZE readings of it give the factor between the
+    counters and real bytes."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 copies of {COPY_PROBE_BYTES} bytes")
 
 
 def cpu_baseline(sc, seconds):
@@ -81,9 +103,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
@@ -94,13 +118,15 @@ def main():
     import torch
 
     import scenarios
-    from paper_2408_07609_amd import Domain
+    from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64, Domain
 
     sc = {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3}[args.config]()
     steps = args.steps if args.steps is not None else sc.steps
     log(f"workload {sc.name}: {len(sc.levels)} levels, {sc.cells} cells, {steps} timed steps")
     d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
-               x0=sc.x0, y0=sc.y0, flags=args.flags, device="cuda:0")
+               x0=sc.x0, y0=sc.y0, flags=args.flags, device="cuda:0",
+               precision=RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64)
+    bpc = BYTES_PER_CELL_FP32_BULK if args.precision == "fp32-bulk" else BYTES_PER_CELL
     d.set_source(*sc.source.astuple())
     init = [d.get_state(k) for k in range(len(sc.levels))]
     zinit = [d.max_inundation(k) for k in range(len(sc.levels))]
@@ -125,14 +151,19 @@ def main():
     log(f"timed {steps} steps: {wall:.3f} s wall, {ev_ms / 1e3:.3f} s by events")
     e_last = d.get_state(len(sc.levels) - 1)[0]
     assert np.all(np.isfinite(e_last)), "non-finite state after the timed run"
-    active, total = d.active_tiles()
+    active, total, active_cells = d.active_tiles()
 
-    prof = d.profile(args.profile_steps)
-    dom = max((k for k in prof if k in BYTES_PER_CELL), key=lambda k: prof[k])
+    prof, prof_cells = d.profile(args.profile_steps)
+    dom = max((k for k in prof if k in bpc), key=lambda k: prof[k])
     launch_ms = prof[dom]
-    alg = BYTES_PER_CELL[dom] * sc.cells
+    # algorithmic bytes of one launch: the per-cell figure times the cells the
+    # launch computes (skipped quiescent tiles move no data)
+    units = prof_cells if dom == "k_fused" else sc.cells
+    alg = bpc[dom] * units
     achieved = alg / (launch_ms * 1e-3) / 1e9
-    log(f"kernel times (ms/launch): {prof}")
+    log(f"kernel times (ms/launch): {prof}; cells per launch {units:.0f}")
+    if args.copy_probe:
+        copy_probe()
 
     value = sc.cells * steps / wall
     out = {
@@ -146,7 +177,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32-bulk (f64 water level)",
         "data": "synthetic",
         "config": {
             "workload": sc.name,
@@ -156,6 +187,7 @@ def main():
             "dt_s": sc.dt,
             "simulated_s": steps * sc.dt,
             "active_tiles": [active, total],
+            "active_cells_last_step": active_cells,
             "flags": args.flags,
         },
         "roofline": {
@@ -165,8 +197,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom, sc.cells),
-            "bytes_per_cell": BYTES_PER_CELL[dom],
+            "traffic": measured_traffic(dom + ("" if args.precision == "fp64" else "_fp32bulk"), sc.name, units),
+            "bytes_per_cell": bpc[dom],
+            "cells_per_launch": units,
             "launch_ms": launch_ms,
             "kernel_ms": prof,
         },

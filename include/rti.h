@@ -58,13 +58,20 @@ enum {
     RTI_EDIVERGED = -7     /* non-finite water level or flux found (sticky) */
 };
 
-enum { RTI_FP64 = 0, RTI_FP32_BULK = 1 };   /* arithmetic of the step; only RTI_FP64 is built */
+/* Arithmetic of the step.  RTI_FP64: everything in binary64.  RTI_FP32_BULK:
+ * h, the maxima and the fluxes M, N are stored in binary32 and the momentum
+ * update runs in binary32; the water level, its continuity update, face
+ * depths, wet/dry tests and the level difference of the pressure term stay
+ * binary64.  Host arrays are binary64 in both cases (converted on copy). */
+enum { RTI_FP64 = 0, RTI_FP32_BULK = 1 };
 enum { RTI_BC_OPEN = 0, RTI_BC_WALL = 1 };  /* root sides */
 enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
 
 /* flags of rti_domain_desc */
 #define RTI_FLAG_NO_GRAPH    0x1u   /* rti_step launches kernels one by one instead of replaying a HIP graph */
 #define RTI_FLAG_NO_ACTIVE   0x2u   /* compute every tile; do not skip quiescent dry tiles */
+#define RTI_FLAG_PHASED      0x4u   /* one kernel per phase (mass, ring mean, momentum, edge fluxes)
+                                       instead of the fused tile kernel; for comparison */
 #define RTI_MAX_LEVELS 16
 
 /* One nest level.  Level 0 is the root (parent = -1); every other level names
@@ -90,7 +97,7 @@ typedef struct {
     double manning_n;                /* Manning roughness [s m^-1/3] (0.025) */
     double dry_eps;                  /* dry threshold on total depth [m] (0.01) */
     int32_t bc[4];                   /* root sides W, E, S, N: RTI_BC_OPEN or RTI_BC_WALL */
-    int32_t precision;               /* RTI_FP64 */
+    int32_t precision;               /* RTI_FP64 or RTI_FP32_BULK (not with RTI_FLAG_PHASED) */
     uint32_t flags;                  /* RTI_FLAG_* */
 } rti_domain_desc;
 
@@ -166,13 +173,16 @@ int rti_sync(rti_domain *dom);
 /* Time the kernels of nsteps steps launched one by one with HIP events on
  * the domain's stream (this advances the state).  ms[k] receives the average
  * duration of kernel kind k per launch, names[k] (may be NULL) a static
- * name; at most cap kinds; *n_kinds the number filled.  Synchronises. */
+ * name; at most cap kinds; *n_kinds the number filled; *active_cells (may be
+ * NULL) the average number of cells in the tiles computed per step.
+ * Synchronises. */
 int rti_profile(rti_domain *dom, int64_t nsteps, double *ms, const char **names, int32_t cap,
-                int32_t *n_kinds);
+                int32_t *n_kinds, double *active_cells);
 
-/* Number of tiles of the last step that were computed (not skipped as
- * quiescent dry land) and the total number of tiles.  Synchronises. */
-int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total);
+/* Tiles computed in the last step (not skipped as quiescent dry land), all
+ * tiles, and the cells inside the computed tiles.  Before the first step every
+ * tile counts as computed.  Synchronises. */
+int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *active_cells);
 
 /* Free the domain's device memory (when the library allocated it), its
  * graphs and the handle.  NULL is a no-op.  Synchronises first. */

@@ -1,0 +1,424 @@
+// rti_fused.hip -- the fused time step of the nested long-wave model on
+// gfx950, FP64: one launch computes, for every active tile of every level,
+// the continuity update (paper Eq. 1), the child-to-parent ring mean (Sec.
+// IV-C), the momentum update (Eqs. 2-3) with the wet/dry rule, the root's open
+// or wall sides, the injection of the new parent fluxes into the children's
+// edge faces, and the running maxima.  State is read from buffer b and the new
+// state written to buffer b^1, so every tile may recompute its halo.
+//
+// Tile = one wavefront.  Lane L owns column c = x0 - 2 + L and the wavefront
+// streams up the rows of the tile: each iteration loads one row of eta, h, M,
+// N (one coalesced 512-byte access per field), computes the new water level
+// of that row, the face quantities of the row (depth, M^2/D, M N/D ...) and
+// the momentum of the row below, whose up/down neighbours are then in
+// registers; left/right neighbours come from the adjacent lanes through DPP
+// wavefront shifts.  Each face quantity is computed once per tile, so the
+// divisions, square roots and cube roots per cell are those of the formula.
+// The 2 halo lanes on each side and the 3 warm-up rows are recomputed by the
+// neighbouring tiles (the loads hit L2), so HBM sees each array about once.
+//
+// Precision: k_fused<double> is the FP64 step.  k_fused<float> is the
+// FP32-bulk step: h, M, N and the maxima are stored in FP32 and the momentum
+// is computed in FP32, while the water level eta, the continuity update, the
+// total depth at faces, the wet/dry tests and the water-level difference of
+// the pressure term stay FP64 (so still water stays still and the level does
+// not accumulate FP32 rounding).
+//
+// Active tiles: before each step k_active lists the tiles to compute.  A tile
+// is skipped only when it and its 8 neighbours were quiescent (every cell dry,
+// every face flux zero) after both of the last two steps and it is not pinned
+// (near a level edge or a child's ring/edge).  Such a tile's step is an exact
+// no-op: its cells and faces and all that its stencil reads keep their values,
+// and both state buffers already hold them.  Dry land therefore costs no
+// bandwidth once it is quiet.
+#include "rti_device.h"
+#include "rti_internal.h"
+
+namespace {
+using namespace rti_dev;
+
+// Value held by lane+1 (from_right) or lane-1 (from_left): wavefront-wide DPP
+// shifts (wave_shl:1 = 0x130, wave_shr:1 = 0x138); the lane without a source
+// receives 0.  Called only in wave-uniform control flow.
+__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+
+__device__ __forceinline__ double from_right(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = dpp_right_i((int)(bits & 0xffffffffLL));
+    const int hi = dpp_right_i((int)(bits >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double from_left(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = dpp_left_i((int)(bits & 0xffffffffLL));
+    const int hi = dpp_left_i((int)(bits >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_right_i(__float_as_int(v))); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left_i(__float_as_int(v))); }
+
+// Face quantities of one x-face (or y-face) of a row, in the flux precision F.
+template <typename F>
+struct FaceQ {
+    F D;          // total depth at the face (if active)
+    F f;          // the face's own flux (M on x-faces, N on y-faces)
+    F cr;         // the cross flux averaged to the face (N on x-faces, M on y-faces)
+    F q;          // f^2 / D
+    F p;          // f * cr / D
+    int act;      // face active under the wet/dry rule (and interior)
+};
+
+// The wet/dry rule and the depth are evaluated in FP64 on the FP64 levels.
+template <typename F>
+__device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, double hb, double eb, double eps,
+                                          F f, F cr)
+{
+    FaceQ<F> o;
+    o.f = f;
+    o.cr = cr;
+    o.D = F(0);
+    o.q = F(0);
+    o.p = F(0);
+    double D;
+    o.act = (interior && face_depth(ha, ea, hb, eb, eps, D)) ? 1 : 0;
+    if (o.act) {
+        const F Df = (F)D;
+        o.D = Df;
+        o.q = (f * f) / Df;
+        o.p = (f * cr) / Df;
+    }
+    return o;
+}
+
+// New flux of an active face: ((1-F) f - Pr - A) / (1+F) with Pr = (gr D) de,
+// A = r (along + cross), F = (fc sqrt(f^2 + cr^2)) / ((D D) cbrt D); de is
+// the FP64 water-level difference.
+template <typename F>
+__device__ __forceinline__ F new_flux(const FaceQ<F> &m, double de, F along, F cross, F r, F gr, F fc)
+{
+    const F D = m.D;
+    const F Pr = (gr * D) * (F)de;
+    const F A = r * (along + cross);
+    const F Fr = (fc * sqrt(m.f * m.f + m.cr * m.cr)) / ((D * D) * cbrt(D));
+    return (((F(1) - Fr) * m.f - Pr) - A) / (F(1) + Fr);
+}
+
+// New water level of parent cell (c, t) when it lies on the ring of one of
+// the level's children: mean of the wet 3x3 child cells after their own
+// continuity update (computed here from the child's buffer b), summed j outer,
+// i inner; not below the parent's ground; unchanged when none is wet.
+template <typename F>
+__device__ double ring_level(const DomainDev &d, const LevelDev &L, int b, int c, int t, double e1, double hpar)
+{
+    for (int q = 0; q < L.n_children; ++q) {
+        const LevelDev &C = d.lv[d.child[L.first_child + q]];
+        const int I = c - C.off_i, J = t - C.off_j;
+        const int fw = C.nx / 3, fh = C.ny / 3;
+        if (I < 0 || J < 0 || I >= fw || J >= fh) continue;
+        if (!(I == 0 || I == fw - 1 || J == 0 || J == fh - 1)) continue;
+        const int CP = C.pitch;
+        const double *ce = C.eta[b];
+        const F *cm = static_cast<const F *>(C.M[b]), *cn = static_cast<const F *>(C.N[b]);
+        const F *ch = static_cast<const F *>(C.h);
+        double s = 0.0;
+        int nw = 0;
+        for (int jj = 3 * J; jj < 3 * J + 3; ++jj) {
+            for (int ii = 3 * I; ii < 3 * I + 3; ++ii) {
+                const int cc = ii + CP * jj;
+                double ec = ce[cc] - C.r * (((double)cm[cc + 1] - (double)cm[cc]) + ((double)cn[cc + CP] - (double)cn[cc]));
+                const double hc = (double)ch[cc];
+                if (hc + ec < 0.0) ec = -hc;
+                if (hc + ec > d.eps) { s += ec; ++nw; }
+            }
+        }
+        if (nw > 0) {
+            const double v = s / (double)nw;
+            const double ground = -hpar;
+            return (v > ground) ? v : ground;
+        }
+        return e1;
+    }
+    return e1;
+}
+
+// The new parent flux on a child's edge goes to the 3 child faces it covers.
+template <typename F>
+__device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c, int r, bool xface, bool yface,
+                             F Mnew, F Nnew)
+{
+    for (int q = 0; q < L.n_children; ++q) {
+        const LevelDev &C = d.lv[d.child[L.first_child + q]];
+        const int fw = C.nx / 3, fh = C.ny / 3;
+        const int CP = C.pitch;
+        if (xface && r >= C.off_j && r < C.off_j + fh && (c == C.off_i || c == C.off_i + fw)) {
+            const int ci = (c == C.off_i) ? 0 : C.nx;
+            const int j0 = 3 * (r - C.off_j);
+            F *cm = static_cast<F *>(C.M[b ^ 1]);
+            cm[ci + CP * j0] = Mnew;
+            cm[ci + CP * (j0 + 1)] = Mnew;
+            cm[ci + CP * (j0 + 2)] = Mnew;
+        }
+        if (yface && c >= C.off_i && c < C.off_i + fw && (r == C.off_j || r == C.off_j + fh)) {
+            const int cj = (r == C.off_j) ? 0 : C.ny;
+            const int i0 = 3 * (c - C.off_i);
+            F *cn = static_cast<F *>(C.N[b ^ 1]);
+            cn[i0 + CP * cj] = Nnew;
+            cn[i0 + 1 + CP * cj] = Nnew;
+            cn[i0 + 2 + CP * cj] = Nnew;
+        }
+    }
+}
+
+__device__ __forceinline__ int level_of_tile(const DomainDev &d, int g)
+{
+    int l = 0;
+    for (int k = 1; k < d.nlev; ++k)
+        if (g >= d.lv[k].tile_base) l = k;
+    return l;
+}
+
+template <typename F>
+__global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
+{
+    // Active tile of this workgroup.  Workgroups go to the 8 XCDs round-robin;
+    // XCD x receives the x-th contiguous slice of the (row-ordered) tile list,
+    // so the halo rows and columns a tile shares with its neighbours sit in
+    // the same L2.
+    const int n_active = *d.count;
+    const int per = (n_active + 7) >> 3;
+    const int slot = (int)(blockIdx.x >> 3);
+    const int pos = (int)(blockIdx.x & 7) * per + slot;
+    if (slot >= per || pos >= n_active) return;
+    const int g = d.list[pos];
+    const int l = level_of_tile(d, g);
+    const LevelDev &L = d.lv[l];
+    const int tl = g - L.tile_base;
+    const int x0 = (tl % L.tiles_x) * RTI_TW;
+    const int y0 = (tl / L.tiles_x) * RTI_TH;
+    const uint8_t info = d.tinfo[g];
+    const bool has_child = (info & TI_CHILD) != 0;
+    const bool root = (l == 0);
+
+    const int lane = (int)threadIdx.x;
+    const int c = x0 - 2 + lane;
+    const int nx = L.nx, ny = L.ny, P = L.pitch;
+    const double r = L.r, eps = d.eps;
+    const F rf = (F)L.r, grf = (F)L.gr, fcf = (F)d.fc;
+    const double *Eb = L.eta[b];
+    const F *Hh = static_cast<const F *>(L.h), *Mb = static_cast<const F *>(L.M[b]);
+    const F *Nb = static_cast<const F *>(L.N[b]);
+    double *Eo = L.eta[b ^ 1];
+    F *Mo = static_cast<F *>(L.M[b ^ 1]), *No = static_cast<F *>(L.N[b ^ 1]), *Z = static_cast<F *>(L.zmax);
+
+    const bool col_cell = (c >= 0) && (c < nx);
+    const bool col_xf = (c >= 0) && (c <= nx);
+    const bool col_xint = (c >= 1) && (c <= nx - 1);
+    const bool out_lane = (lane >= 2) && (lane < 2 + RTI_TW);
+
+    auto ld_eta = [&](int row) -> double {
+        return (col_cell && row >= 0 && row < ny) ? Eb[c + P * row] : 0.0;
+    };
+    auto ld_h = [&](int row) -> double {
+        return (col_cell && row >= 0 && row < ny) ? (double)Hh[c + P * row] : 0.0;
+    };
+    auto ld_xf = [&](int row) -> F {
+        return (col_xf && row >= 0 && row < ny) ? Mb[c + P * row] : F(0);
+    };
+    auto ld_yf = [&](int row) -> F {
+        return (col_cell && row >= 0 && row <= ny) ? Nb[c + P * row] : F(0);
+    };
+
+    const int t0 = y0 - 2;
+    const int t1 = min(y0 + RTI_TH, ny + 1);   // last iteration; it writes row t1 - 1
+
+    // Rolling window (suffix p = row t-1, pp = row t-2).
+    F Ny_t = ld_yf(t0);
+    F NyL_t = from_left(Ny_t);
+    double e1p = 0.0, e1pp = 0.0, e1Lp = 0.0, Hp = 0.0, Hpp = 0.0, HLp = 0.0;
+    F Mxp = F(0), MxRp = F(0);
+    FaceQ<F> xp{}, xpp{}, yp{}, ypp{};
+    bool quiet = true;
+
+    // Prefetched raw row.
+    double E_n = ld_eta(t0), H_n = ld_h(t0);
+    F Mx_n = ld_xf(t0), Ny_n = ld_yf(t0 + 1);
+
+    for (int t = t0; t <= t1; ++t) {
+        const double E_t = E_n, H_t = H_n;
+        const F Mx_t = Mx_n, Ny_t1 = Ny_n;
+        if (t < t1) {
+            E_n = ld_eta(t + 1);
+            H_n = ld_h(t + 1);
+            Mx_n = ld_xf(t + 1);
+            Ny_n = ld_yf(t + 2);
+        }
+        const bool row_cell = (t >= 0) && (t < ny);
+
+        // Continuity of row t (Eq. 1, FP64), then the child ring overlay.
+        const F MxR_t = from_right(Mx_t);
+        double e1 = 0.0;
+        if (col_cell && row_cell) {
+            e1 = E_t - r * (((double)MxR_t - (double)Mx_t) + ((double)Ny_t1 - (double)Ny_t));
+            if (H_t + e1 < 0.0) e1 = -H_t;
+            if (has_child) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
+        }
+
+        // Face quantities: x-face c of row t, y-face c at j = t.
+        const double e1L = from_left(e1);
+        const double HL = from_left(H_t);
+        const F NyL_t1 = from_left(Ny_t1);
+        const F nb = F(0.25) * ((NyL_t + NyL_t1) + (Ny_t + Ny_t1));
+        const FaceQ<F> xt = face_q<F>(col_xint && row_cell, HL, e1L, H_t, e1, eps, Mx_t, nb);
+        const F mb = F(0.25) * ((Mxp + MxRp) + (Mx_t + MxR_t));
+        const FaceQ<F> yt = face_q<F>(col_cell && t >= 1 && t <= ny - 1, Hp, e1p, H_t, e1, eps, Ny_t, mb);
+
+        // Neighbours of row t-1 along x (wave-uniform).
+        const int xl_act = dpp_left_i(xp.act), xr_act = dpp_right_i(xp.act);
+        const F xl_f = from_left(xp.f), xr_f = from_right(xp.f);
+        const F xl_q = from_left(xp.q), xr_q = from_right(xp.q);
+        const int yl_act = dpp_left_i(yp.act), yr_act = dpp_right_i(yp.act);
+        const F yl_cr = from_left(yp.cr), yr_cr = from_right(yp.cr);
+        const F yl_p = from_left(yp.p), yr_p = from_right(yp.p);
+
+        // Momentum and outputs of row (x-faces, cells) / face (y-faces) rr = t-1.
+        const int rr = t - 1;
+        if (rr >= y0 && rr <= ny && out_lane) {
+            F Mnew = F(0), Nnew = F(0);
+            const bool xf_here = col_xf && rr < ny;
+            const bool yf_here = col_cell;
+            if (xf_here) {
+                if (col_xint) {
+                    if (xp.act) {
+                        const F X = upwind_diff<F>(xp.f, xp.q, xl_act != 0, xl_f, xl_q, xr_act != 0, xr_f, xr_q);
+                        const F Y = upwind_diff<F>(xp.cr, xp.p, xpp.act != 0, xpp.cr, xpp.p, xt.act != 0, xt.cr, xt.p);
+                        Mnew = new_flux<F>(xp, e1p - e1Lp, X, Y, rf, grf, fcf);
+                    }
+                } else if (root) {
+                    Mnew = (F)((c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
+                                        : (d.bc[1] ? 0.0 : radiate(d.g, eps, HLp, e1Lp, 1.0)));
+                }
+                if (col_xint || root) Mo[c + P * rr] = Mnew;
+            }
+            if (yf_here) {
+                if (rr >= 1 && rr <= ny - 1) {
+                    if (yp.act) {
+                        const F Yd = upwind_diff<F>(yp.f, yp.q, ypp.act != 0, ypp.f, ypp.q, yt.act != 0, yt.f, yt.q);
+                        const F Xd = upwind_diff<F>(yp.cr, yp.p, yl_act != 0, yl_cr, yl_p, yr_act != 0, yr_cr, yr_p);
+                        Nnew = new_flux<F>(yp, e1p - e1pp, Yd, Xd, rf, grf, fcf);
+                    }
+                } else if (root) {
+                    Nnew = (F)((rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
+                                         : (d.bc[3] ? 0.0 : radiate(d.g, eps, Hpp, e1pp, 1.0)));
+                }
+                if ((rr >= 1 && rr <= ny - 1) || root) No[c + P * rr] = Nnew;
+            }
+            if (col_cell && rr < ny) {
+                Eo[c + P * rr] = e1p;
+                const F v = (F)((Hp > 0.0) ? e1p : Hp + e1p);
+                const int zc = c + P * rr;
+                if (v > Z[zc]) Z[zc] = v;
+                quiet = quiet && !(Hp + e1p > eps);
+            }
+            quiet = quiet && (Mnew == F(0)) && (Nnew == F(0));
+            if (has_child)
+                inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_here && rr >= 1 && rr <= ny - 1, Mnew, Nnew);
+        }
+
+        // Roll the window.
+        xpp = xp; xp = xt;
+        ypp = yp; yp = yt;
+        e1pp = e1p; e1p = e1; e1Lp = e1L;
+        Hpp = Hp; Hp = H_t; HLp = HL;
+        Mxp = Mx_t; MxRp = MxR_t;
+        Ny_t = Ny_t1; NyL_t = NyL_t1;
+    }
+
+    // Quiescence history of the tile: bit1 <- bit0, bit0 <- this step.
+    const bool all_quiet = __all(quiet ? 1 : 0);
+    if (lane == 0) {
+        const uint8_t old = d.tflag[g];
+        const uint8_t nw = (info & TI_PINNED) ? 0 : (uint8_t)(((old & 1u) << 1) | (all_quiet ? 1u : 0u));
+        d.tflag[g] = nw;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Active tiles of the coming step, in tile order, by one workgroup of 1024
+// threads: in each round every thread tests one tile (its 9 flag bytes are
+// loaded together), a block-wide exclusive scan places the round's active
+// tiles after those of the previous rounds.
+__device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_active)
+{
+    if (all_active) return 1;
+    if (d.tinfo[g] & TI_PINNED) return 1;
+    const int l = level_of_tile(d, g);
+    const LevelDev &L = d.lv[l];
+    const int tl = g - L.tile_base;
+    const int tx = tl % L.tiles_x, ty = tl / L.tiles_x;
+    unsigned acc = 3u;
+    #pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        #pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = tx + dx, y = ty + dy;
+            const bool in = x >= 0 && x < L.tiles_x && y >= 0 && y < L.tiles_y;
+            const unsigned f = in ? (unsigned)d.tflag[L.tile_base + y * L.tiles_x + x] : 3u;
+            acc &= f;
+        }
+    }
+    return (acc & 3u) == 3u ? 0 : 1;
+}
+
+__global__ __launch_bounds__(1024) void k_active(DomainDev d, int all_active)
+{
+    __shared__ int wsum[16];
+    const int n = d.ntiles;
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    int base = 0;
+    for (int r0 = 0; r0 < n; r0 += 1024) {
+        const int g = r0 + tid;
+        const int a = (g < n) ? tile_active(d, g, all_active) : 0;
+        int incl = a;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            const int s = wsum[k];
+            before += (k < w) ? s : 0;
+            total += s;
+        }
+        if (a) d.list[base + before + incl - 1] = g;
+        base += total;
+        __syncthreads();
+    }
+    if (tid == 0) *d.count = base;
+}
+
+}  // namespace
+
+hipError_t launch_active(const DomainDev &d, int all_active, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_active, dim3(1), dim3(1024), 0, s, d, all_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(const DomainDev &d, int b, hipStream_t s)
+{
+    // One workgroup per tile at most; the 8-way XCD slicing needs a multiple of 8.
+    const int grid = (d.ntiles + 7) / 8 * 8;
+    if (d.bulk32)
+        hipLaunchKernelGGL(k_fused<float>, dim3(grid), dim3(64), 0, s, d, b);
+    else
+        hipLaunchKernelGGL(k_fused<double>, dim3(grid), dim3(64), 0, s, d, b);
+    return hipGetLastError();
+}

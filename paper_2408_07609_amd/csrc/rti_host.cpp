@@ -46,21 +46,54 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct LevelPlan {
     int nx, ny, pitch, parent, off_i, off_j;
     double dx, ox, oy;
-    size_t cells_bytes, xf_bytes, yf_bytes;   // one pitched array of each kind
+    size_t eta_bytes;                       // one pitched FP64 cell array (eta)
+    size_t cells_bytes, xf_bytes, yf_bytes; // one pitched array of h/maxima, M, N in the bulk precision
     int tiles_x, tiles_y, s_tiles_x, s_tiles_y;
 };
 
 struct Plan {
     std::vector<LevelPlan> lv;
+    std::vector<uint8_t> tinfo;   // static bits per fused-kernel tile (TI_*)
+    std::vector<int32_t> tcells;  // cells of the level inside each tile
+    size_t elem = sizeof(double); // element size of h, maxima, M, N
     size_t bytes = 0;
     int ntiles = 0, s_ntiles = 0;
 };
 
-bool level_has_child(const rti_domain_desc *d, int k)
+// Static bits of every tile.  A tile's extended region (its cells plus the
+// 2-cell halo its stencil reads, plus one for safety) decides: TI_EDGE when it
+// reaches within 3 cells of the level's outer faces (open sides, injected
+// child edges); TI_CHILD when it reaches within 3 parent cells of a child's
+// footprint boundary (ring cells, edge faces).  Both pin the tile.
+void tile_info(const rti_domain_desc *d, Plan &plan)
 {
-    for (int q = k + 1; q < d->n_levels; ++q)
-        if (d->levels[q].parent == k) return true;
-    return false;
+    plan.tinfo.assign(plan.ntiles, 0);
+    plan.tcells.assign(plan.ntiles, 0);
+    int base = 0;
+    for (int l = 0; l < d->n_levels; ++l) {
+        const LevelPlan &p = plan.lv[l];
+        for (int ty = 0; ty < p.tiles_y; ++ty) {
+            for (int tx = 0; tx < p.tiles_x; ++tx) {
+                const int ax = tx * RTI_TW - 3, bx = tx * RTI_TW + RTI_TW + 2;
+                const int ay = ty * RTI_TH - 3, by = ty * RTI_TH + RTI_TH + 2;
+                uint8_t bits = 0;
+                if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) bits |= TI_EDGE | TI_PINNED;
+                for (int k = l + 1; k < d->n_levels; ++k) {
+                    const rti_level_desc &C = d->levels[k];
+                    if (C.parent != l) continue;
+                    const int fx0 = C.off_i, fx1 = C.off_i + C.nx / 3 - 1;   // footprint, inclusive
+                    const int fy0 = C.off_j, fy1 = C.off_j + C.ny / 3 - 1;
+                    const bool meets_outer = ax <= fx1 + 3 && bx >= fx0 - 3 && ay <= fy1 + 3 && by >= fy0 - 3;
+                    const bool inside_inner = ax >= fx0 + 3 && bx <= fx1 - 3 && ay >= fy0 + 3 && by <= fy1 - 3;
+                    if (meets_outer && !inside_inner) bits |= TI_CHILD | TI_PINNED;
+                }
+                plan.tinfo[base + ty * p.tiles_x + tx] = bits;
+                const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(RTI_TH, p.ny - ty * RTI_TH);
+                plan.tcells[base + ty * p.tiles_x + tx] = std::max(0, w) * std::max(0, hgt);
+            }
+        }
+        base += p.tiles_x * p.tiles_y;
+    }
 }
 
 // Validate the descriptor and lay the domain out in device memory.
@@ -75,9 +108,13 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         return fail(RTI_EINVAL, "dt, dx0, g, dry_eps must be positive and finite, manning_n >= 0");
     for (int s = 0; s < 4; ++s)
         if (d->bc[s] != RTI_BC_OPEN && d->bc[s] != RTI_BC_WALL) return fail(RTI_EINVAL, "bc[%d] = %d", s, d->bc[s]);
-    if (d->precision == RTI_FP32_BULK) return fail(RTI_EINVAL, "RTI_FP32_BULK is not built; use RTI_FP64");
-    if (d->precision != RTI_FP64) return fail(RTI_EINVAL, "precision %d unknown", d->precision);
-    if (d->flags & ~(RTI_FLAG_NO_GRAPH | RTI_FLAG_NO_ACTIVE)) return fail(RTI_EINVAL, "unknown flags 0x%x", d->flags);
+    if (d->precision != RTI_FP64 && d->precision != RTI_FP32_BULK)
+        return fail(RTI_EINVAL, "precision %d unknown", d->precision);
+    if (d->precision == RTI_FP32_BULK && (d->flags & RTI_FLAG_PHASED))
+        return fail(RTI_EINVAL, "the per-phase kernels are FP64 only");
+    plan.elem = (d->precision == RTI_FP32_BULK) ? sizeof(float) : sizeof(double);
+    if (d->flags & ~(RTI_FLAG_NO_GRAPH | RTI_FLAG_NO_ACTIVE | RTI_FLAG_PHASED))
+        return fail(RTI_EINVAL, "unknown flags 0x%x", d->flags);
 
     plan.lv.assign(d->n_levels, LevelPlan{});
     for (int k = 0; k < d->n_levels; ++k) {
@@ -104,9 +141,10 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         const long long pitch = (long long)align_up((size_t)L.nx + 1, 32);
         if (pitch * (long long)(L.ny + 1) >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
         p.pitch = (int)pitch;
-        p.cells_bytes = align_up((size_t)pitch * (size_t)L.ny * sizeof(double), kAlign);
+        p.eta_bytes = align_up((size_t)pitch * (size_t)L.ny * sizeof(double), kAlign);
+        p.cells_bytes = align_up((size_t)pitch * (size_t)L.ny * plan.elem, kAlign);
         p.xf_bytes = p.cells_bytes;
-        p.yf_bytes = align_up((size_t)pitch * (size_t)(L.ny + 1) * sizeof(double), kAlign);
+        p.yf_bytes = align_up((size_t)pitch * (size_t)(L.ny + 1) * plan.elem, kAlign);
     }
     for (int a = 1; a < d->n_levels; ++a) {
         for (int b = a + 1; b < d->n_levels; ++b) {
@@ -142,14 +180,15 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         p.s_tiles_y = (p.ny + 3) / 4;
         ntiles += p.tiles_x * p.tiles_y;
         s_ntiles += p.s_tiles_x * p.s_tiles_y;
-        // h, zmax, eta x2, M x2, N x2, tile flags
-        bytes += 4 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
-        bytes += align_up((size_t)p.tiles_x * p.tiles_y, kAlign);
+        // eta x2 (FP64); h, zmax, M x2, N x2 (bulk precision)
+        bytes += 2 * p.eta_bytes + 2 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
     }
-    bytes += kAlign;   // control block: divergence flag, counters
+    // tile info, tile flags, active list, control block (count, divergence flag)
+    bytes += 2 * align_up((size_t)ntiles, kAlign) + align_up((size_t)ntiles * 4, kAlign) + kAlign;
     plan.bytes = bytes;
     plan.ntiles = ntiles;
     plan.s_ntiles = s_ntiles;
+    tile_info(d, plan);
     return RTI_OK;
 }
 
@@ -164,7 +203,8 @@ struct rti_domain {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     void *mem = nullptr;                 // base of the carved memory
     bool owns_mem = false;
-    int *ctrl = nullptr;                 // [0] divergence flag
+    int *ctrl = nullptr;                 // [0] active tile count, [1] divergence flag
+    uint8_t *tinfo = nullptr;
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;
     uint32_t flags = 0;
@@ -182,17 +222,22 @@ int carve(rti_domain *D)
     for (int k = 0; k < (int)D->plan.lv.size(); ++k) {
         const LevelPlan &pl = D->plan.lv[k];
         LevelDev &L = D->dev.lv[k];
-        L.h = reinterpret_cast<double *>(take(pl.cells_bytes));
-        L.zmax = reinterpret_cast<double *>(take(pl.cells_bytes));
-        L.eta[0] = reinterpret_cast<double *>(take(pl.cells_bytes));
-        L.eta[1] = reinterpret_cast<double *>(take(pl.cells_bytes));
-        L.M[0] = reinterpret_cast<double *>(take(pl.xf_bytes));
-        L.M[1] = reinterpret_cast<double *>(take(pl.xf_bytes));
-        L.N[0] = reinterpret_cast<double *>(take(pl.yf_bytes));
-        L.N[1] = reinterpret_cast<double *>(take(pl.yf_bytes));
-        L.flag = reinterpret_cast<uint8_t *>(take(align_up((size_t)pl.tiles_x * pl.tiles_y, kAlign)));
+        L.eta[0] = reinterpret_cast<double *>(take(pl.eta_bytes));
+        L.eta[1] = reinterpret_cast<double *>(take(pl.eta_bytes));
+        L.h = take(pl.cells_bytes);
+        L.zmax = take(pl.cells_bytes);
+        L.M[0] = take(pl.xf_bytes);
+        L.M[1] = take(pl.xf_bytes);
+        L.N[0] = take(pl.yf_bytes);
+        L.N[1] = take(pl.yf_bytes);
     }
+    const size_t nt = (size_t)D->plan.ntiles;
+    D->tinfo = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
+    D->dev.tinfo = D->tinfo;
+    D->dev.tflag = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
+    D->dev.list = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
     D->ctrl = reinterpret_cast<int *>(take(kAlign));
+    D->dev.count = D->ctrl;         // ctrl[0]: active tiles
     return RTI_OK;
 }
 
@@ -211,10 +256,42 @@ int get_rows(rti_domain *D, double *dst, int w, const double *src, int pitch, in
     return RTI_OK;
 }
 
+// The same for arrays in the bulk precision (h, maxima, M, N): FP64 host rows
+// are converted to FP32 on the host first when the domain runs FP32-bulk.
+int put_rows_b(rti_domain *D, void *dst, int pitch, const double *src, int w, int rows)
+{
+    if (D->plan.elem == sizeof(double)) return put_rows(D, static_cast<double *>(dst), pitch, src, w, rows);
+    std::vector<float> tmp((size_t)w * rows);
+    for (size_t k = 0; k < tmp.size(); ++k) tmp[k] = (float)src[k];
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)pitch * sizeof(float), tmp.data(), (size_t)w * sizeof(float),
+                             (size_t)w * sizeof(float), rows, hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    return RTI_OK;
+}
+
+int get_rows_b(rti_domain *D, double *dst, int w, const void *src, int pitch, int rows)
+{
+    if (D->plan.elem == sizeof(double)) return get_rows(D, dst, w, static_cast<const double *>(src), pitch, rows);
+    std::vector<float> tmp((size_t)w * rows);
+    HIP_TRY(hipMemcpy2DAsync(tmp.data(), (size_t)w * sizeof(float), src, (size_t)pitch * sizeof(float),
+                             (size_t)w * sizeof(float), rows, hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    for (size_t k = 0; k < tmp.size(); ++k) dst[k] = (double)tmp[k];
+    return RTI_OK;
+}
+
 int check_level(const rti_domain *D, int level)
 {
     if (!D) return fail(RTI_EINVAL, "domain is NULL");
     if (level < 0 || level >= D->dev.nlev) return fail(RTI_EINVAL, "level %d outside [0, %d)", level, D->dev.nlev);
+    return RTI_OK;
+}
+
+// Any host-side change of the state forgets the quiescence history, so the
+// next two steps compute every tile.
+int forget_quiet(rti_domain *D)
+{
+    HIP_TRY(hipMemsetAsync(D->dev.tflag, 0, (size_t)D->plan.ntiles, D->stream));
     return RTI_OK;
 }
 
@@ -236,18 +313,52 @@ int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &
         HIP_TRY(hipMemsetAsync(L.M[b], 0, p.xf_bytes, D->stream));
         HIP_TRY(hipMemsetAsync(L.N[b], 0, p.yf_bytes, D->stream));
     }
-    int rc = put_rows(D, L.zmax, p.pitch, z.data(), p.nx, p.ny);
+    int rc = put_rows_b(D, L.zmax, p.pitch, z.data(), p.nx, p.ny);
     if (rc) return rc;
+    if ((rc = forget_quiet(D))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));   // host vectors die on return
     return RTI_OK;
 }
 
 int launch_step(rti_domain *D, int b, hipStream_t s)
 {
-    HIP_TRY(launch_mass(D->dev, b, s));
-    HIP_TRY(launch_jnz(D->dev, b, s));
-    HIP_TRY(launch_momentum(D->dev, b, s));
-    HIP_TRY(launch_jnq(D->dev, b, s));
+    if (D->flags & RTI_FLAG_PHASED) {
+        HIP_TRY(launch_mass(D->dev, b, s));
+        HIP_TRY(launch_jnz(D->dev, b, s));
+        HIP_TRY(launch_momentum(D->dev, b, s));
+        HIP_TRY(launch_jnq(D->dev, b, s));
+    } else {
+        HIP_TRY(launch_active(D->dev, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
+        HIP_TRY(launch_fused(D->dev, b, s));
+    }
+    return RTI_OK;
+}
+
+// Cells inside the tiles of the current active list (synchronises).
+int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
+{
+    if (D->flags & RTI_FLAG_PHASED) {
+        int64_t n = 0;
+        for (const auto &p : D->plan.lv) n += (int64_t)p.nx * p.ny;
+        *tiles = D->dev.s_ntiles;
+        *cells = n;
+        return RTI_OK;
+    }
+    int n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, D->ctrl, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    if (D->steps == 0) n = D->dev.ntiles;
+    std::vector<int32_t> list(n);
+    if (D->steps > 0 && n > 0) {
+        HIP_TRY(hipMemcpyAsync(list.data(), D->dev.list, sizeof(int32_t) * n, hipMemcpyDeviceToHost, D->stream));
+        HIP_TRY(hipStreamSynchronize(D->stream));
+    } else {
+        for (int g = 0; g < n; ++g) list[g] = g;
+    }
+    int64_t c = 0;
+    for (int g : list) c += D->plan.tcells[g];
+    *tiles = n;
+    *cells = c;
     return RTI_OK;
 }
 
@@ -353,6 +464,7 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         dv.s_ntiles = plan.s_ntiles;
         for (int s = 0; s < 4; ++s) dv.bc[s] = desc->bc[s];
         dv.eps = desc->dry_eps;
+        dv.bulk32 = (desc->precision == RTI_FP32_BULK) ? 1 : 0;
         dv.g = desc->g;
         dv.fc = 0.5 * desc->dt * desc->g * desc->manning_n * desc->manning_n;
         int base = 0, sbase = 0;
@@ -365,19 +477,34 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             L.s_tiles_x = p.s_tiles_x; L.s_tile_base = sbase;
             base += p.tiles_x * p.tiles_y;
             sbase += p.s_tiles_x * p.s_tiles_y;
-            L.has_children = level_has_child(desc, k) ? 1 : 0;
             L.r = desc->dt / p.dx;
             L.gr = desc->g * L.r;
         }
+        {
+            int nc = 0;
+            for (int p = 0; p < dv.nlev; ++p) {
+                dv.lv[p].first_child = nc;
+                dv.lv[p].n_children = 0;
+                for (int k = p + 1; k < dv.nlev; ++k) {
+                    if (desc->levels[k].parent == p) {
+                        dv.child[nc++] = k;
+                        dv.lv[p].n_children += 1;
+                    }
+                }
+            }
+        }
         carve(D);
         e = hipMemsetAsync(D->mem, 0, plan.bytes, D->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(D->tinfo, plan.tinfo.data(), plan.tinfo.size(), hipMemcpyHostToDevice, D->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(D->stream);
         if (e != hipSuccess) {
             rti_domain_destroy(D);
-            return fail(RTI_EHIP, "hipMemsetAsync failed: %s", hipGetErrorString(e));
+            return fail(RTI_EHIP, "initialising device memory failed: %s", hipGetErrorString(e));
         }
         for (int k = 0; k < dv.nlev; ++k) {
             const LevelPlan &p = plan.lv[k];
-            rc = put_rows(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
+            rc = put_rows_b(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
             if (rc) { rti_domain_destroy(D); return rc; }
             std::vector<double> eta((size_t)p.nx * p.ny);
             const double *h = desc->levels[k].h;
@@ -407,7 +534,7 @@ int rti_set_source(rti_domain *D, const rti_source *src)
         for (int k = 0; k < D->dev.nlev; ++k) {
             const LevelPlan &p = D->plan.lv[k];
             std::vector<double> h((size_t)p.nx * p.ny), eta(h.size());
-            int rc = get_rows(D, h.data(), p.nx, D->dev.lv[k].h, p.pitch, p.ny);
+            int rc = get_rows_b(D, h.data(), p.nx, D->dev.lv[k].h, p.pitch, p.ny);
             if (rc) return rc;
             HIP_TRY(hipStreamSynchronize(D->stream));
             for (int j = 0; j < p.ny; ++j) {
@@ -457,7 +584,7 @@ int rti_set_eta(rti_domain *D, int32_t level, const double *eta0)
         std::vector<double> h(n), eta(eta0, eta0 + n);
         for (size_t c = 0; c < n; ++c)
             if (!std::isfinite(eta[c])) return fail(RTI_EINVAL, "eta0 not finite at cell %zu", c);
-        rc = get_rows(D, h.data(), p.nx, D->dev.lv[level].h, p.pitch, p.ny);
+        rc = get_rows_b(D, h.data(), p.nx, D->dev.lv[level].h, p.pitch, p.ny);
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(D->stream));
         return install_initial(D, level, h.data(), eta);
@@ -514,10 +641,10 @@ int rti_run(rti_domain *D, double t_end)
         int rc = rti_step(D, target - D->steps);
         if (rc) return rc;
     }
-    HIP_TRY(launch_zero_int(D->ctrl, 1, D->stream));
-    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl, D->stream));
+    HIP_TRY(launch_zero_int(D->ctrl + 1, 1, D->stream));
+    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl + 1, D->stream));
     int flag = 0;
-    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl + 1, sizeof(int), hipMemcpyDeviceToHost, D->stream));
     HIP_TRY(hipStreamSynchronize(D->stream));
     if (flag) {
         D->diverged = true;
@@ -532,7 +659,7 @@ int rti_max_inundation(rti_domain *D, int32_t level, double *out)
     if (rc) return rc;
     if (!out) return fail(RTI_EINVAL, "out is NULL");
     const LevelPlan &p = D->plan.lv[level];
-    rc = get_rows(D, out, p.nx, D->dev.lv[level].zmax, p.pitch, p.ny);
+    rc = get_rows_b(D, out, p.nx, D->dev.lv[level].zmax, p.pitch, p.ny);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
@@ -545,8 +672,8 @@ int rti_get_state(rti_domain *D, int32_t level, double *eta, double *M, double *
     const LevelPlan &p = D->plan.lv[level];
     const LevelDev &L = D->dev.lv[level];
     if (eta && (rc = get_rows(D, eta, p.nx, L.eta[D->cur], p.pitch, p.ny))) return rc;
-    if (M && (rc = get_rows(D, M, p.nx + 1, L.M[D->cur], p.pitch, p.ny))) return rc;
-    if (N && (rc = get_rows(D, N, p.nx, L.N[D->cur], p.pitch, p.ny + 1))) return rc;
+    if (M && (rc = get_rows_b(D, M, p.nx + 1, L.M[D->cur], p.pitch, p.ny))) return rc;
+    if (N && (rc = get_rows_b(D, N, p.nx, L.N[D->cur], p.pitch, p.ny + 1))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
 }
@@ -559,9 +686,10 @@ int rti_set_state(rti_domain *D, int32_t level, const double *eta, const double 
     const LevelDev &L = D->dev.lv[level];
     for (int b = 0; b < 2; ++b) {
         if (eta && (rc = put_rows(D, L.eta[b], p.pitch, eta, p.nx, p.ny))) return rc;
-        if (M && (rc = put_rows(D, L.M[b], p.pitch, M, p.nx + 1, p.ny))) return rc;
-        if (N && (rc = put_rows(D, L.N[b], p.pitch, N, p.nx, p.ny + 1))) return rc;
+        if (M && (rc = put_rows_b(D, L.M[b], p.pitch, M, p.nx + 1, p.ny))) return rc;
+        if (N && (rc = put_rows_b(D, L.N[b], p.pitch, N, p.nx, p.ny + 1))) return rc;
     }
+    if ((rc = forget_quiet(D))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     D->diverged = false;
     return RTI_OK;
@@ -573,7 +701,8 @@ int rti_set_max(rti_domain *D, int32_t level, const double *zmax)
     if (rc) return rc;
     if (!zmax) return fail(RTI_EINVAL, "zmax is NULL");
     const LevelPlan &p = D->plan.lv[level];
-    if ((rc = put_rows(D, D->dev.lv[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
+    if ((rc = put_rows_b(D, D->dev.lv[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
+    if ((rc = forget_quiet(D))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
 }
@@ -585,7 +714,8 @@ int rti_steps_done(const rti_domain *D, int64_t *steps)
     return RTI_OK;
 }
 
-int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, int32_t cap, int32_t *n_kinds)
+int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, int32_t cap, int32_t *n_kinds,
+                double *avg_cells)
 {
     if (!D || !ms || !n_kinds || cap < 1 || nsteps < 1) return fail(RTI_EINVAL, "bad argument");
     static const char *kNames[K_NKINDS] = {"k_mass", "k_jnz", "k_momentum", "k_jnq", "k_fused", "k_active", "k_finite"};
@@ -594,24 +724,38 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     int rc = RTI_OK;
+    const bool phased = (D->flags & RTI_FLAG_PHASED) != 0;
+    double cell_sum = 0.0;
     for (int64_t s = 0; s < nsteps && rc == RTI_OK; ++s) {
         const int b = D->cur;
+        int kinds[4];
+        int nk = 0;
         hipError_t e = hipEventRecord(ev[0], D->stream);
-        if (e == hipSuccess) e = launch_mass(D->dev, b, D->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
-        if (e == hipSuccess) e = launch_jnz(D->dev, b, D->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
-        if (e == hipSuccess) e = launch_momentum(D->dev, b, D->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3], D->stream);
-        if (e == hipSuccess) e = launch_jnq(D->dev, b, D->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[4], D->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+        if (phased) {
+            if (e == hipSuccess) e = launch_mass(D->dev, b, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
+            if (e == hipSuccess) e = launch_jnz(D->dev, b, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
+            if (e == hipSuccess) e = launch_momentum(D->dev, b, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[3], D->stream);
+            if (e == hipSuccess) e = launch_jnq(D->dev, b, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[4], D->stream);
+            kinds[0] = K_MASS; kinds[1] = K_JNZ; kinds[2] = K_MOMENTUM; kinds[3] = K_JNQ;
+            nk = 4;
+        } else {
+            if (e == hipSuccess) e = launch_active(D->dev, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
+            if (e == hipSuccess) e = launch_fused(D->dev, b, D->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
+            kinds[0] = K_ACTIVE; kinds[1] = K_FUSED;
+            nk = 2;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[nk]);
         if (e != hipSuccess) {
             rc = fail(RTI_EHIP, "profiling step failed: %s", hipGetErrorString(e));
             break;
         }
-        const int kinds[4] = {K_MASS, K_JNZ, K_MOMENTUM, K_JNQ};
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < nk; ++q) {
             if ((kinds[q] == K_JNZ || kinds[q] == K_JNQ) && D->dev.nlev < 2) continue;
             float t = 0.0f;
             (void)hipEventElapsedTime(&t, ev[q], ev[q + 1]);
@@ -620,6 +764,11 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
         }
         D->cur ^= 1;
         D->steps += 1;
+        if (avg_cells) {
+            int64_t t = 0, c = 0;
+            if ((rc = active_cells(D, &t, &c))) break;
+            cell_sum += (double)c;
+        }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (rc) return rc;
@@ -631,14 +780,16 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
         ++n;
     }
     *n_kinds = n;
+    if (avg_cells) *avg_cells = cell_sum / (double)nsteps;
     return RTI_OK;
 }
 
-int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total)
+int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total, int64_t *cells)
 {
-    if (!D || !active || !total) return fail(RTI_EINVAL, "NULL argument");
-    *total = D->dev.s_ntiles;
-    *active = D->dev.s_ntiles;
+    if (!D || !active || !total || !cells) return fail(RTI_EINVAL, "NULL argument");
+    int rc = active_cells(D, active, cells);
+    if (rc) return rc;
+    *total = (D->flags & RTI_FLAG_PHASED) ? D->dev.s_ntiles : D->dev.ntiles;
     return RTI_OK;
 }
 

@@ -1,5 +1,6 @@
 // rti_internal.h -- device-side data layout shared by the host runtime
-// (rti_host.cpp) and the kernels (rti_kernels.hip).  Not part of the ABI.
+// (rti_host.cpp) and the kernels (rti_kernels.hip, rti_fused.hip).  Not part
+// of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,20 +8,32 @@
 
 #define RTI_MAX_LEVELS_DEV 16
 
+// Tile of the fused kernel: one wavefront of 64 lanes covers 64 columns and
+// writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
+// right); it streams up RTI_TH output rows (plus 3 rows of pipeline warm-up).
+#define RTI_TW 60
+#define RTI_TH 32
+
+// Static per-tile bits (host-computed at create).
+#define TI_PINNED 0x1u      // never skipped and never reported quiescent
+#define TI_CHILD 0x2u       // the tile's extended region meets a child's ring or edge faces
+#define TI_EDGE 0x4u        // the tile's extended region meets the level's outer faces
+
 // One level on the device.  Every field of a level shares one row pitch P
-// (a multiple of 32 doubles, >= nx + 1): cell (i,j), x-face (i,j) and
+// (a multiple of 32 elements, >= nx + 1): cell (i,j), x-face (i,j) and
 // y-face (i,j) all live at element i + P*j of their array.  eta and the
 // fluxes are double-buffered; buffer b of a step is read, buffer b^1 written.
+// eta is always FP64; h, the maxima and the fluxes are FP64, or FP32 when the
+// domain runs in FP32-bulk precision (DomainDev::bulk32).
 struct LevelDev {
     int32_t nx, ny, pitch;
     int32_t parent, off_i, off_j;
     int32_t tiles_x, tiles_y, tile_base;   // tile grid of the fused kernel and its first global tile
     int32_t s_tiles_x, s_tile_base;        // 64x4 tile grid of the per-phase kernels
-    int32_t has_children;
+    int32_t first_child, n_children;       // children are levels first_child .. (listed in child[])
     double r, gr;                          // dt/dx and g*dt/dx
-    double *h, *zmax;
-    double *eta[2], *M[2], *N[2];
-    uint8_t *flag;                         // per tile: bit0 quiescent after the step just done, bit1 the step before, bit2 pinned active
+    double *eta[2];
+    void *h, *zmax, *M[2], *N[2];          // element type: double, or float when bulk32
 };
 
 struct DomainDev {
@@ -28,23 +41,27 @@ struct DomainDev {
     int32_t ntiles;                        // fused-kernel tiles over all levels
     int32_t s_ntiles;                      // per-phase-kernel tiles over all levels
     int32_t bc[4];
+    int32_t bulk32;                        // 1: h, maxima, M, N stored and the momentum computed in FP32
+    int32_t child[RTI_MAX_LEVELS_DEV];     // level indices grouped by parent: lv[p].first_child indexes here
     double eps, fc, g;                     // dry threshold, dt/2 g n^2, gravity
+    const uint8_t *tinfo;                  // ntiles static bits (TI_*)
+    uint8_t *tflag;                        // ntiles: bit0 quiescent after the last step, bit1 after the one before
+    int32_t *list;                         // ntiles: active tiles of the current step, in tile order
+    int32_t *count;                        // [0] number of active tiles
     LevelDev lv[RTI_MAX_LEVELS_DEV];
 };
-
-// Tile of the fused kernel: TW output columns, TH output rows.
-#define RTI_TW 60
-#define RTI_TH 32
 
 // Kernel kinds (for profiling).
 enum {
     K_MASS = 0, K_JNZ, K_MOMENTUM, K_JNQ, K_FUSED, K_ACTIVE, K_FINITE, K_NKINDS
 };
 
-// Launchers (rti_kernels.hip); all enqueue on stream and return the launch status.
+// Launchers; all enqueue on stream and return the launch status.
 hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnz(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+hipError_t launch_active(const DomainDev &d, int all_active, hipStream_t s);
+hipError_t launch_fused(const DomainDev &d, int b, hipStream_t s);

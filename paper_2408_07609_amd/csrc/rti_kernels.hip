@@ -13,8 +13,10 @@
 // order stated next to it (no reassociation; the library is built with
 // -ffp-contract=off so no multiply-add is fused).
 #include "rti_internal.h"
+#include "rti_device.h"
 
 namespace {
+using namespace rti_dev;
 
 __device__ __forceinline__ int level_of_stile(const DomainDev &d, int blk)
 {
@@ -23,39 +25,6 @@ __device__ __forceinline__ int level_of_stile(const DomainDev &d, int blk)
     for (int k = 1; k < d.nlev; ++k)
         if (blk >= d.lv[k].s_tile_base) l = k;
     return l;
-}
-
-// Wet/dry rule of a face between cells A and B: both wet -> D = (hA+hB)/2 +
-// (eA+eB)/2; one wet (say A) -> flux only if eA > -hB, D = eA + hB; both dry
-// -> none; and none whenever D <= eps.
-__device__ __forceinline__ bool face_depth(double ha, double ea, double hb, double eb, double eps, double &D)
-{
-    const bool wa = ha + ea > eps, wb = hb + eb > eps;
-    if (wa && wb) {
-        D = 0.5 * (ha + hb) + 0.5 * (ea + eb);
-    } else if (wa) {
-        if (!(ea > -hb)) return false;
-        D = ea + hb;
-    } else if (wb) {
-        if (!(eb > -ha)) return false;
-        D = eb + ha;
-    } else {
-        return false;
-    }
-    return D > eps;
-}
-
-// First-order upwind difference of a face momentum flux v along one axis;
-// s carries the velocity sign at the face, (m) the neighbour behind, (p) the
-// one ahead.  A face without flow takes the flux of neighbours flowing in.
-__device__ __forceinline__ double upwind_diff(double s, double v, bool okm, double sm, double vm,
-                                              bool okp, double sp, double vp)
-{
-    if (s > 0.0) return okm ? v - vm : 0.0;
-    if (s < 0.0) return okp ? vp - v : 0.0;
-    const double a = (okm && sm > 0.0) ? vm : 0.0;
-    const double c = (okp && sp < 0.0) ? vp : 0.0;
-    return (-a) + c;
 }
 
 struct View {
@@ -150,15 +119,6 @@ __device__ double ymom(const View &v, double eps, double r, double gr, double fc
     return (((1.0 - F) * n - Pr) - A) / (1.0 + F);
 }
 
-// Open side of the root: flux = sign * (sqrt(g h) * eta) of the boundary cell;
-// none when the cell is land or dry.
-__device__ __forceinline__ double radiate(double g, double eps, double h, double e, double sign)
-{
-    if (!(h > 0.0) || !(h + e > eps)) return 0.0;
-    const double c = sqrt(g * h);
-    return sign * (c * e);
-}
-
 // ---------------------------------------------------------------------------
 // Continuity, Eq. (1): eta' = eta - r ((M_{i+1} - M_i) + (N_{j+1} - N_j)),
 // then clipped to the ground (h + eta' < 0 -> eta' = -h).
@@ -171,10 +131,10 @@ __global__ __launch_bounds__(256) void k_mass(DomainDev d, int b)
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
     if (i >= L.nx || j >= L.ny) return;
     const int P = L.pitch;
-    const double *M = L.M[b], *N = L.N[b];
+    const double *M = static_cast<const double *>(L.M[b]), *N = static_cast<const double *>(L.N[b]);
     const int c = i + P * j;
     double e = L.eta[b][c] - L.r * ((M[c + 1] - M[c]) + (N[c + P] - N[c]));
-    const double hh = L.h[c];
+    const double hh = static_cast<const double *>(L.h)[c];
     if (hh + e < 0.0) e = -hh;
     L.eta[b ^ 1][c] = e;
 }
@@ -202,19 +162,20 @@ __global__ __launch_bounds__(256) void k_jnz(DomainDev d, int b)
         I = (q & 1) ? fw - 1 : 0;
     }
     const double *ce = C.eta[b ^ 1];
+    const double *ch = static_cast<const double *>(C.h);
     const int CP = C.pitch;
     double s = 0.0;
     int nw = 0;
     for (int jj = 3 * J; jj < 3 * J + 3; ++jj) {
         for (int ii = 3 * I; ii < 3 * I + 3; ++ii) {
             const double e = ce[ii + CP * jj];
-            if (C.h[ii + CP * jj] + e > d.eps) { s += e; ++nw; }
+            if (ch[ii + CP * jj] + e > d.eps) { s += e; ++nw; }
         }
     }
     if (nw > 0) {
         const int pc = (C.off_i + I) + Pl.pitch * (C.off_j + J);
         const double v = s / (double)nw;
-        const double ground = -Pl.h[pc];
+        const double ground = -static_cast<const double *>(Pl.h)[pc];
         Pl.eta[b ^ 1][pc] = (v > ground) ? v : ground;
     }
 }
@@ -231,24 +192,26 @@ __global__ __launch_bounds__(256) void k_momentum(DomainDev d, int b)
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
     if (i >= L.nx || j >= L.ny) return;
     const int P = L.pitch;
-    View v{L.h, L.eta[b ^ 1], L.M[b], L.N[b], L.nx, L.ny, P};
-    double *Mo = L.M[b ^ 1], *No = L.N[b ^ 1];
+    const double *Lh = static_cast<const double *>(L.h);
+    View v{Lh, L.eta[b ^ 1], static_cast<const double *>(L.M[b]), static_cast<const double *>(L.N[b]), L.nx, L.ny, P};
+    double *Mo = static_cast<double *>(L.M[b ^ 1]), *No = static_cast<double *>(L.N[b ^ 1]);
+    double *Zm = static_cast<double *>(L.zmax);
     const int c = i + P * j;
 
     if (i >= 1) Mo[c] = xmom(v, d.eps, L.r, L.gr, d.fc, i, j);
     if (j >= 1) No[c] = ymom(v, d.eps, L.r, L.gr, d.fc, i, j);
 
     if (l == 0) {
-        const double hc = L.h[c], ec = v.eta[c];
+        const double hc = Lh[c], ec = v.eta[c];
         if (i == 0) Mo[c] = d.bc[0] ? 0.0 : radiate(d.g, d.eps, hc, ec, -1.0);
         if (i == L.nx - 1) Mo[c + 1] = d.bc[1] ? 0.0 : radiate(d.g, d.eps, hc, ec, 1.0);
         if (j == 0) No[c] = d.bc[2] ? 0.0 : radiate(d.g, d.eps, hc, ec, -1.0);
         if (j == L.ny - 1) No[c + P] = d.bc[3] ? 0.0 : radiate(d.g, d.eps, hc, ec, 1.0);
     }
 
-    const double hc = L.h[c], e = v.eta[c];
+    const double hc = Lh[c], e = v.eta[c];
     const double val = (hc > 0.0) ? e : hc + e;
-    if (val > L.zmax[c]) L.zmax[c] = val;
+    if (val > Zm[c]) Zm[c] = val;
 }
 
 // Parent -> child: every child boundary face takes the flux of the parent
@@ -262,8 +225,8 @@ __global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
     const int ny = C.ny, nx = C.nx;
     const int I0 = C.off_i, J0 = C.off_j, fw = nx / 3, fh = ny / 3;
     const int CP = C.pitch, PP = Pl.pitch;
-    const double *PM = Pl.M[b ^ 1], *PN = Pl.N[b ^ 1];
-    double *CM = C.M[b ^ 1], *CN = C.N[b ^ 1];
+    const double *PM = static_cast<const double *>(Pl.M[b ^ 1]), *PN = static_cast<const double *>(Pl.N[b ^ 1]);
+    double *CM = static_cast<double *>(C.M[b ^ 1]), *CN = static_cast<double *>(C.N[b ^ 1]);
     if (k < ny) {
         CM[0 + CP * k] = PM[I0 + PP * (J0 + k / 3)];
     } else if (k < 2 * ny) {
@@ -279,6 +242,7 @@ __global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
 }
 
 // Any non-finite water level or flux in buffer b sets *flag.
+template <typename F>
 __global__ __launch_bounds__(256) void k_finite(DomainDev d, int b, int *flag)
 {
     const int blk = blockIdx.x;
@@ -288,7 +252,8 @@ __global__ __launch_bounds__(256) void k_finite(DomainDev d, int b, int *flag)
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
     if (i >= L.nx || j >= L.ny) return;
     const int c = i + L.pitch * j;
-    const bool bad = !isfinite(L.eta[b][c]) || !isfinite(L.M[b][c]) || !isfinite(L.N[b][c]);
+    const bool bad = !isfinite(L.eta[b][c]) || !isfinite((double)static_cast<const F *>(L.M[b])[c])
+                     || !isfinite((double)static_cast<const F *>(L.N[b])[c]);
     if (bad) atomicOr(flag, 1);
 }
 
@@ -349,7 +314,10 @@ hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s)
 
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finite, dim3(d.s_ntiles), dim3(256), 0, s, d, b, flag);
+    if (d.bulk32)
+        hipLaunchKernelGGL(k_finite<float>, dim3(d.s_ntiles), dim3(256), 0, s, d, b, flag);
+    else
+        hipLaunchKernelGGL(k_finite<double>, dim3(d.s_ntiles), dim3(256), 0, s, d, b, flag);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ RTI_OK, RTI_EINVAL, RTI_ENOMEM, RTI_EHIP, RTI_ECFL, RTI_ENEST, RTI_ESTATE, RTI_E
 RTI_FP64, RTI_FP32_BULK = 0, 1
 RTI_BC_OPEN, RTI_BC_WALL = 0, 1
 RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
-RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE = 0x1, 0x2
+RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED = 0x1, 0x2, 0x4
 RTI_MAX_LEVELS = 16
 
 _dptr = ctypes.POINTER(ctypes.c_double)
@@ -66,8 +66,9 @@ FUNCTIONS = {
     "rti_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rti_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "rti_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dptr, ctypes.POINTER(ctypes.c_char_p),
-                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
-    "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
+    "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "rti_domain_destroy": (None, [ctypes.c_void_p]),
     "rti_last_error": (ctypes.c_char_p, []),
     "rti_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -160,19 +161,22 @@ def rti_sync(dom: int):
     _check(LIB.rti_sync(dom))
 
 
-def rti_profile(dom: int, nsteps: int) -> dict:
+def rti_profile(dom: int, nsteps: int):
+    """Returns ({kernel name: average ms per launch}, average cells computed per step)."""
     cap = 16
     ms = (ctypes.c_double * cap)()
     names = (ctypes.c_char_p * cap)()
     n = ctypes.c_int32(0)
-    _check(LIB.rti_profile(dom, int(nsteps), ms, names, cap, ctypes.byref(n)))
-    return {names[k].decode(): float(ms[k]) for k in range(n.value)}
+    cells = ctypes.c_double(0.0)
+    _check(LIB.rti_profile(dom, int(nsteps), ms, names, cap, ctypes.byref(n), ctypes.byref(cells)))
+    return {names[k].decode(): float(ms[k]) for k in range(n.value)}, float(cells.value)
 
 
 def rti_active_tiles(dom: int):
-    a, t = ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(LIB.rti_active_tiles(dom, ctypes.byref(a), ctypes.byref(t)))
-    return int(a.value), int(t.value)
+    """Returns (computed tiles, all tiles, cells in the computed tiles) of the last step."""
+    a, t, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(LIB.rti_active_tiles(dom, ctypes.byref(a), ctypes.byref(t), ctypes.byref(c)))
+    return int(a.value), int(t.value), int(c.value)
 
 
 def rti_domain_destroy(dom: int | None):
@@ -215,11 +219,12 @@ class Domain:
     tensor; stream: torch's current stream (or the one given)."""
 
     def __init__(self, levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 0, 0), x0=0.0, y0=0.0,
-                 flags=0, device="cuda:0", stream=None):
+                 flags=0, device="cuda:0", stream=None, precision=RTI_FP64):
         import torch
         self.levels = [dict(nx=int(lv["nx"]), ny=int(lv["ny"])) for lv in levels]
         self.dt = float(dt)
-        desc, keep = make_desc(levels, dx0, dt, g, manning_n, dry_eps, bc, x0, y0, RTI_FP64, flags)
+        self.precision = int(precision)
+        desc, keep = make_desc(levels, dx0, dt, g, manning_n, dry_eps, bc, x0, y0, precision, flags)
         self.footprint = rti_domain_footprint(desc)
         dev = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -290,6 +295,7 @@ class Domain:
         return out
 
     def profile(self, nsteps):
+        """({kernel: ms per launch}, cells computed per step) over nsteps eager steps."""
         return rti_profile(self._h, nsteps)
 
     def active_tiles(self):

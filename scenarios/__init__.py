@@ -165,11 +165,14 @@ class _Coast:
         hs = np.array([k[1] for k in self.knots])
         sea = np.interp(s, ks, hs)
         deep = sea > 500.0
-        if self.bumps:
-            bump = np.zeros_like(X)
+        if self.bumps and deep.any():
+            Xd, Yd = X[deep], Y[deep]
+            bump = np.zeros_like(Xd)
             for (bx, by) in self.bumps:
-                bump = bump + 200.0 * np.exp(-((X - bx) ** 2 + (Y - by) ** 2) / (2.0 * self.bump_sigma ** 2))
-            sea = np.where(deep, sea - np.minimum(bump, sea - 500.0), sea)
+                bump = bump + 200.0 * np.exp(-((Xd - bx) ** 2 + (Yd - by) ** 2) / (2.0 * self.bump_sigma ** 2))
+            sd = sea[deep]
+            sea = sea.copy()
+            sea[deep] = sd - np.minimum(bump, sd - 500.0)
         land = -np.minimum(self.zmax, self.slope * (-s))
         return np.where(s > 0.0, sea, land)
 

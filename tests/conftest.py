@@ -9,4 +9,4 @@ for p in (ROOT, os.path.dirname(os.path.abspath(__file__))):
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: longer CPU test")
+    config.addinivalue_line("markers", "slow: longer CPU test (tens of seconds)")

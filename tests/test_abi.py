@@ -80,7 +80,9 @@ def test_validation_codes():
     # bad arguments
     assert code_of([ok], dt=0.0) == rti.RTI_EINVAL
     assert code_of([ok], bc=(0, 0, 2, 0)) == rti.RTI_EINVAL
-    assert code_of([ok], precision=rti.RTI_FP32_BULK) == rti.RTI_EINVAL
+    assert code_of([ok], precision=rti.RTI_FP32_BULK) == rti.RTI_OK
+    assert code_of([ok], precision=rti.RTI_FP32_BULK, flags=rti.RTI_FLAG_PHASED) == rti.RTI_EINVAL
+    assert code_of([ok], precision=7) == rti.RTI_EINVAL
     assert code_of([ok], flags=0x100) == rti.RTI_EINVAL
     bad = np.full((30, 30), 100.0)
     bad[3, 4] = np.nan

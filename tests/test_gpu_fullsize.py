@@ -1,0 +1,80 @@
+"""Parity at the full sizes of the workloads, in the launch configuration the
+benchmark times (fused kernel, active tiles, HIP graphs).
+
+The oracle computes every cell of a few steps from a seeded random state of
+the full grid (wet/dry mix, both flux signs, every exchange), so every output
+of those steps is compared, not a sample.  Skipping quiescent tiles is checked
+to be exact at full size against the same run with skipping off.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_domain(sc, flags=0):
+    from paper_2408_07609_amd import Domain
+    return Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
+                  x0=sc.x0, y0=sc.y0, flags=flags)
+
+
+def run_random(sc, steps, seed):
+    d = gpu_domain(sc)
+    o = oracle.OracleDomain(**sc.oracle_kwargs())
+    for k, (e, M, N) in enumerate(scenarios.random_state(sc, seed, flux=1.0)):
+        h = sc.levels[k]["h"]
+        z = np.where(h > 0, e, h + e)
+        d.set_state(k, e, M, N)
+        d.set_max(k, z)
+        o.set_state(k, eta=e, M=M, N=N, zmax=z)
+        print(f"level {k} loaded", flush=True)
+    d.step(steps)
+    d.sync()
+    o.step(steps)
+    worst = {}
+    for k in range(len(sc.levels)):
+        e, M, N = d.get_state(k)
+        eo, Mo, No = o.get_state(k)
+        worst[k] = (float(np.abs(e - eo).max()), float(np.abs(M - Mo).max()), float(np.abs(N - No).max()),
+                    float(np.abs(d.max_inundation(k) - o.max_inundation(k)).max()))
+        print(f"level {k}: max|d eta| {worst[k][0]:.2e} |dM| {worst[k][1]:.2e} |dN| {worst[k][2]:.2e} "
+              f"|d max| {worst[k][3]:.2e}", flush=True)
+    d.close()
+    return worst
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_size_steps():
+    sc = scenarios.c2()
+    for k, w in run_random(sc, 3, seed=202).items():
+        assert max(w) <= 1e-9, f"level {k}: {w}"
+
+
+@pytest.mark.timeout(1200)
+def test_c3_full_size_steps():
+    sc = scenarios.c3()
+    for k, w in run_random(sc, 2, seed=303).items():
+        assert max(w) <= 1e-9, f"level {k}: {w}"
+
+
+@pytest.mark.timeout(900)
+def test_c2_tile_skipping_is_exact():
+    """Configuration 2 from its source for 600 steps: the run that skips
+    quiescent dry tiles equals, bit for bit, the run that computes every tile,
+    and it did skip tiles."""
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE
+    sc = scenarios.c2()
+    a, b = gpu_domain(sc), gpu_domain(sc, flags=RTI_FLAG_NO_ACTIVE)
+    for d in (a, b):
+        d.set_source(*sc.source.astuple())
+        d.step(600)
+        d.sync()
+    active, total, cells = a.active_tiles()
+    print(f"active tiles {active} of {total} ({cells} of {sc.cells} cells)")
+    assert active < 0.9 * total
+    for k in range(len(sc.levels)):
+        for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
+            assert np.array_equal(x, y), f"level {k}"
