@@ -1,0 +1,83 @@
+"""Configuration 2 at full size for the whole run (4 levels, 10.02 M cells,
+18,000 steps of 0.2 s = 3600 s) on the GPU, in the benchmark's launch
+configuration, against the oracle's sampled outputs stored in
+tests/golden/c2_full_run.npz (written by tests/golden/make_golden.py, which
+calls only the oracle).
+
+FP64: max |d eta| <= 1e-9 m and the same on the maxima at every sampled cell,
+fluxes within 1e-9 of their scale.  FP32-bulk: the stated error bound of that
+precision (1e-3 m on eta and the maxima), printed with the RMS.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+import scenarios
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "c2_full_run.npz")
+ORACLE_SRC = os.path.join(os.path.dirname(HERE), "oracle", "rti_oracle.c")
+
+
+def load_golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/c2_full_run.npz not generated")
+    g = np.load(GOLDEN, allow_pickle=False)
+    with open(ORACLE_SRC, "rb") as f:
+        if str(g["oracle_sha256"]) != hashlib.sha256(f.read()).hexdigest():
+            pytest.fail("the golden file was written by another oracle source; rerun tests/golden/make_golden.py")
+    return g
+
+
+def run_c2(precision):
+    from paper_2408_07609_amd import Domain
+    sc = scenarios.c2()
+    d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
+               x0=sc.x0, y0=sc.y0, precision=precision)
+    d.set_source(*sc.source.astuple())
+    d.run(sc.steps * sc.dt)
+    return sc, d
+
+
+def compare(sc, d, g):
+    res = []
+    for k in range(len(sc.levels)):
+        i, j = g[f"l{k}_i"], g[f"l{k}_j"]
+        e, M, N = d.get_state(k)
+        z = d.max_inundation(k)
+        fs = max(1.0, float(g[f"l{k}_stats"][3]), float(g[f"l{k}_stats"][4]))
+        de = np.abs(e[j, i] - g[f"l{k}_eta"])
+        res.append(dict(eta_max=float(de.max()), eta_rms=float(np.sqrt(np.mean(de ** 2))),
+                        zmax=float(np.abs(z[j, i] - g[f"l{k}_zmax"]).max()),
+                        M=float(np.abs(M[j, i] - g[f"l{k}_M"]).max() / fs),
+                        N=float(np.abs(N[j, i] - g[f"l{k}_N"]).max() / fs),
+                        eta_sum_rel=float(abs(e.sum() - g[f"l{k}_stats"][0]) / max(1.0, np.abs(e).sum())),
+                        inundated=int(np.count_nonzero((sc.levels[k]["h"] <= 0) & (z > 0.01))),
+                        inundated_oracle=int(g[f"l{k}_inundated"])))
+        print(f"level {k}: {res[-1]}", flush=True)
+    return res
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_run_fp64_matches_oracle():
+    from paper_2408_07609_amd import RTI_FP64
+    g = load_golden()
+    sc, d = run_c2(RTI_FP64)
+    assert d.steps == int(g["steps"]) == sc.steps
+    for k, r in enumerate(compare(sc, d, g)):
+        assert r["eta_max"] <= 1e-9 and r["zmax"] <= 1e-9, f"level {k}: {r}"
+        assert r["M"] <= 1e-9 and r["N"] <= 1e-9, f"level {k}: {r}"
+        assert r["inundated"] == r["inundated_oracle"]
+    assert compare and int(g["l3_inundated"]) > 0, "the run never inundated the finest level"
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_run_fp32_bulk_error():
+    from paper_2408_07609_amd import RTI_FP32_BULK
+    g = load_golden()
+    sc, d = run_c2(RTI_FP32_BULK)
+    for k, r in enumerate(compare(sc, d, g)):
+        assert r["eta_max"] <= 1e-3 and r["zmax"] <= 1e-3, f"level {k}: {r}"
