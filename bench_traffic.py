@@ -10,7 +10,7 @@ that factor and by the cells of the workload give its HBM bytes per computed
 cell, stored with the kernel source hash so bench.py can tell when they are
 stale.
 
-    python bench_traffic.py FETCH_CSV WRITE_CSV --cells N --workload NAME
+    python bench_traffic.py FETCH_CSV WRITE_CSV --cells N --workload NAME [--key k_fused_fp32bulk]
 """
 from __future__ import annotations
 
@@ -42,7 +42,8 @@ def main():
     ap.add_argument("write_csv")
     ap.add_argument("--cells", type=int, required=True)
     ap.add_argument("--workload", required=True)
-    ap.add_argument("--kernel", default="k_fused")
+    ap.add_argument("--kernel", default="k_fused", help="substring of the kernel name")
+    ap.add_argument("--key", default=None, help="entry name in the json (default: --kernel)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     out = {}
@@ -59,7 +60,7 @@ def main():
         if not ker:
             sys.exit(f"no {args.kernel} dispatch in {path}")
         per[which] = (sum(ker) / len(ker)) * 1024 / factors[which]
-    out[args.kernel] = {
+    out[args.key or args.kernel] = {
         "bytes_per_cell": (per["fetch"] + per["write"]) / args.cells,
         "fetch_bytes_per_launch": per["fetch"],
         "write_bytes_per_launch": per["write"],

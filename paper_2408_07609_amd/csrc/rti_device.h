@@ -13,19 +13,16 @@ namespace rti_dev {
 // -> none; and none whenever D <= eps.
 __device__ __forceinline__ bool face_depth(double ha, double ea, double hb, double eb, double eps, double &D)
 {
+    // Every candidate is formed and the rule picks one (no branches: the
+    // lanes of a wavefront take different cases).
     const bool wa = ha + ea > eps, wb = hb + eb > eps;
-    if (wa && wb) {
-        D = 0.5 * (ha + hb) + 0.5 * (ea + eb);
-    } else if (wa) {
-        if (!(ea > -hb)) return false;
-        D = ea + hb;
-    } else if (wb) {
-        if (!(eb > -ha)) return false;
-        D = eb + ha;
-    } else {
-        return false;
-    }
-    return D > eps;
+    const double Dboth = 0.5 * (ha + hb) + 0.5 * (ea + eb);
+    const double Da = ea + hb, Db = eb + ha;
+    const bool both = wa & wb;
+    const bool only_a = wa & !wb & (ea > -hb);
+    const bool only_b = wb & !wa & (eb > -ha);
+    D = both ? Dboth : (only_a ? Da : Db);
+    return (both | only_a | only_b) & (D > eps);
 }
 
 // First-order upwind difference of a face momentum flux v along one axis;
@@ -34,11 +31,12 @@ __device__ __forceinline__ bool face_depth(double ha, double ea, double hb, doub
 template <typename F>
 __device__ __forceinline__ F upwind_diff(F s, F v, bool okm, F sm, F vm, bool okp, F sp, F vp)
 {
-    if (s > F(0)) return okm ? v - vm : F(0);
-    if (s < F(0)) return okp ? vp - v : F(0);
-    const F a = (okm && sm > F(0)) ? vm : F(0);
-    const F c = (okp && sp < F(0)) ? vp : F(0);
-    return (-a) + c;
+    const F behind = okm ? v - vm : F(0);
+    const F ahead = okp ? vp - v : F(0);
+    const F a = (okm & (sm > F(0))) ? vm : F(0);
+    const F c = (okp & (sp < F(0))) ? vp : F(0);
+    const F tie = (-a) + c;
+    return (s > F(0)) ? behind : ((s < F(0)) ? ahead : tie);
 }
 
 // Open side of the root: flux = sign * (sqrt(g h) * eta) of the boundary cell;
@@ -48,6 +46,62 @@ __device__ __forceinline__ double radiate(double g, double eps, double h, double
     if (!(h > 0.0) || !(h + e > eps)) return 0.0;
     const double c = sqrt(g * h);
     return sign * (c * e);
+}
+
+// 1/x: the hardware reciprocal refined by one Newton step (x is a positive
+// depth or 1 + F, far from denormals).
+__device__ __forceinline__ double recip(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
+// x^(-1/3) for x > 0: a binary32 estimate 2^(-log2(x)/3) refined by Newton
+// steps of z <- z (4 - x z^3) / 3 (quadratic convergence: two steps take the
+// ~1e-7 estimate to binary64 rounding, one step suffices for binary32).
+__device__ __forceinline__ double rcbrt(double x)
+{
+    double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)x));
+    for (int k = 0; k < 2; ++k) {
+        const double z3 = (z * z) * z;
+        z = (z * (4.0 - x * z3)) * (1.0 / 3.0);
+    }
+    return z;
+}
+__device__ __forceinline__ float rcbrt(float x)
+{
+    float z = __builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf(x));
+    const float z3 = (z * z) * z;
+    return (z * (4.0f - x * z3)) * (1.0f / 3.0f);
+}
+
+// Momentum flux quantity a*b/D given 1/D.
+template <typename F>
+__device__ __forceinline__ F over_depth(F a, F b, F invD)
+{
+    return (a * b) * invD;
+}
+
+// New flux of an active face: ((1-F) f - Pr - A) / (1+F) with Pr = (gr D) de,
+// A = r (along + cross) and the semi-implicit Manning factor
+// F = (dt/2) g n^2 sqrt(f^2 + cr^2) / D^(7/3), D^(-7/3) = (D^(-1/3))^7.
+template <typename F>
+__device__ __forceinline__ F momentum_update(F f, F cr, F D, F de, F along, F cross, F r, F gr, F fc)
+{
+    const F Pr = (gr * D) * de;
+    const F A = r * (along + cross);
+    const F z = rcbrt(D);
+    const F z2 = z * z;
+    const F z7 = (z2 * z2) * (z2 * z);
+    const F Fr = (fc * sqrt(f * f + cr * cr)) * z7;
+    return (((F(1) - Fr) * f - Pr) - A) * recip(F(1) + Fr);
 }
 
 }  // namespace rti_dev

@@ -78,34 +78,28 @@ template <typename F>
 __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, double hb, double eb, double eps,
                                           F f, F cr)
 {
+    // Computed on every lane; an inactive face carries D = 1 (a safe value
+    // that is never used) and q = p = 0.
     FaceQ<F> o;
+    double D;
+    const bool act = face_depth(ha, ea, hb, eb, eps, D) & interior;
+    const F Df = act ? (F)D : F(1);
+    const F iD = recip(Df);
+    o.act = act ? 1 : 0;
+    o.D = Df;
     o.f = f;
     o.cr = cr;
-    o.D = F(0);
-    o.q = F(0);
-    o.p = F(0);
-    double D;
-    o.act = (interior && face_depth(ha, ea, hb, eb, eps, D)) ? 1 : 0;
-    if (o.act) {
-        const F Df = (F)D;
-        o.D = Df;
-        o.q = (f * f) / Df;
-        o.p = (f * cr) / Df;
-    }
+    o.q = act ? over_depth(f, f, iD) : F(0);
+    o.p = act ? over_depth(f, cr, iD) : F(0);
     return o;
 }
 
-// New flux of an active face: ((1-F) f - Pr - A) / (1+F) with Pr = (gr D) de,
-// A = r (along + cross), F = (fc sqrt(f^2 + cr^2)) / ((D D) cbrt D); de is
-// the FP64 water-level difference.
+// New flux of an active face (momentum_update); de is the FP64 water-level
+// difference across the face.
 template <typename F>
 __device__ __forceinline__ F new_flux(const FaceQ<F> &m, double de, F along, F cross, F r, F gr, F fc)
 {
-    const F D = m.D;
-    const F Pr = (gr * D) * (F)de;
-    const F A = r * (along + cross);
-    const F Fr = (fc * sqrt(m.f * m.f + m.cr * m.cr)) / ((D * D) * cbrt(D));
-    return (((F(1) - Fr) * m.f - Pr) - A) / (F(1) + Fr);
+    return momentum_update<F>(m.f, m.cr, m.D, (F)de, along, cross, r, gr, fc);
 }
 
 // New water level of parent cell (c, t) when it lies on the ring of one of
@@ -189,7 +183,7 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     // XCD x receives the x-th contiguous slice of the (row-ordered) tile list,
     // so the halo rows and columns a tile shares with its neighbours sit in
     // the same L2.
-    const int n_active = *d.count;
+    const int n_active = d.count[b];
     const int per = (n_active + 7) >> 3;
     const int slot = (int)(blockIdx.x >> 3);
     const int pos = (int)(blockIdx.x & 7) * per + slot;
@@ -215,23 +209,33 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     double *Eo = L.eta[b ^ 1];
     F *Mo = static_cast<F *>(L.M[b ^ 1]), *No = static_cast<F *>(L.N[b ^ 1]), *Z = static_cast<F *>(L.zmax);
 
+
     const bool col_cell = (c >= 0) && (c < nx);
     const bool col_xf = (c >= 0) && (c <= nx);
     const bool col_xint = (c >= 1) && (c <= nx - 1);
     const bool out_lane = (lane >= 2) && (lane < 2 + RTI_TW);
 
+    // Every array is padded with zeros: 2 columns on the left, at least 61 on
+    // the right of the last face, 3 rows below and 3 above; the padding is
+    // never written.  So a lane can load any (c, row) of its tile without a
+    // bounds test and gets exactly 0 outside the level.  Offsets are taken
+    // from the start of the padded allocation (always >= 0), one 32-bit
+    // element offset per row shared by every array.
+    const uint32_t pad = (uint32_t)(3 * P + 2);
+    const char *Eb_a = reinterpret_cast<const char *>(Eb - pad);
+    const char *Hh_a = reinterpret_cast<const char *>(Hh - pad);
+    const char *Mb_a = reinterpret_cast<const char *>(Mb - pad);
+    const char *Nb_a = reinterpret_cast<const char *>(Nb - pad);
+    const uint32_t u0 = (uint32_t)(x0 + lane);                    // element offset of (c, -3)
+    auto ofs = [&](int row) -> uint32_t { return u0 + (uint32_t)P * (uint32_t)(row + 3); };
     auto ld_eta = [&](int row) -> double {
-        return (col_cell && row >= 0 && row < ny) ? Eb[c + P * row] : 0.0;
+        return *reinterpret_cast<const double *>(Eb_a + ofs(row) * (uint32_t)sizeof(double));
     };
     auto ld_h = [&](int row) -> double {
-        return (col_cell && row >= 0 && row < ny) ? (double)Hh[c + P * row] : 0.0;
+        return (double)*reinterpret_cast<const F *>(Hh_a + ofs(row) * (uint32_t)sizeof(F));
     };
-    auto ld_xf = [&](int row) -> F {
-        return (col_xf && row >= 0 && row < ny) ? Mb[c + P * row] : F(0);
-    };
-    auto ld_yf = [&](int row) -> F {
-        return (col_cell && row >= 0 && row <= ny) ? Nb[c + P * row] : F(0);
-    };
+    auto ld_xf = [&](int row) -> F { return *reinterpret_cast<const F *>(Mb_a + ofs(row) * (uint32_t)sizeof(F)); };
+    auto ld_yf = [&](int row) -> F { return *reinterpret_cast<const F *>(Nb_a + ofs(row) * (uint32_t)sizeof(F)); };
 
     const int t0 = y0 - 2;
     const int t1 = min(y0 + RTI_TH, ny + 1);   // last iteration; it writes row t1 - 1
@@ -244,28 +248,40 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     FaceQ<F> xp{}, xpp{}, yp{}, ypp{};
     bool quiet = true;
 
-    // Prefetched raw row.
+    // Output arrays through the same padded offsets.
+    char *Eo_a = reinterpret_cast<char *>(Eo - pad);
+    char *Mo_a = reinterpret_cast<char *>(Mo - pad);
+    char *No_a = reinterpret_cast<char *>(No - pad);
+    char *Z_a = reinterpret_cast<char *>(Z - pad);
+    auto ld_z = [&](int row) -> F { return *reinterpret_cast<const F *>(Z_a + ofs(row) * (uint32_t)sizeof(F)); };
+
+    // Memory pipeline: the raw row t+1 and the maxima of row t are loaded at
+    // the top of iteration t, so the loads have a whole row of arithmetic to
+    // arrive and the maxima update never waits on a load.
     double E_n = ld_eta(t0), H_n = ld_h(t0);
     F Mx_n = ld_xf(t0), Ny_n = ld_yf(t0 + 1);
+    F Zp = F(0);                                   // maxima of row t-1
 
     for (int t = t0; t <= t1; ++t) {
         const double E_t = E_n, H_t = H_n;
         const F Mx_t = Mx_n, Ny_t1 = Ny_n;
+        F Z_t = F(0);
         if (t < t1) {
             E_n = ld_eta(t + 1);
             H_n = ld_h(t + 1);
             Mx_n = ld_xf(t + 1);
             Ny_n = ld_yf(t + 2);
         }
+        if (t >= y0) Z_t = ld_z(t);
         const bool row_cell = (t >= 0) && (t < ny);
 
         // Continuity of row t (Eq. 1, FP64), then the child ring overlay.
         const F MxR_t = from_right(Mx_t);
-        double e1 = 0.0;
-        if (col_cell && row_cell) {
-            e1 = E_t - r * (((double)MxR_t - (double)Mx_t) + ((double)Ny_t1 - (double)Ny_t));
-            if (H_t + e1 < 0.0) e1 = -H_t;
-            if (has_child) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
+        double e1 = E_t - r * (((double)MxR_t - (double)Mx_t) + ((double)Ny_t1 - (double)Ny_t));
+        e1 = (H_t + e1 < 0.0) ? -H_t : e1;
+        e1 = (col_cell && row_cell) ? e1 : 0.0;
+        if (has_child) {
+            if (col_cell && row_cell) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
         }
 
         // Face quantities: x-face c of row t, y-face c at j = t.
@@ -286,47 +302,41 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
         const F yl_p = from_left(yp.p), yr_p = from_right(yp.p);
 
         // Momentum and outputs of row (x-faces, cells) / face (y-faces) rr = t-1.
+        // The momentum of both faces is evaluated on every lane (inactive
+        // faces carry safe values) and the rule selects the result; only the
+        // stores depend on the lane.
         const int rr = t - 1;
-        if (rr >= y0 && rr <= ny && out_lane) {
-            F Mnew = F(0), Nnew = F(0);
+        if (rr >= y0 && rr <= ny) {
+            const F X = upwind_diff<F>(xp.f, xp.q, xl_act != 0, xl_f, xl_q, xr_act != 0, xr_f, xr_q);
+            const F Y = upwind_diff<F>(xp.cr, xp.p, xpp.act != 0, xpp.cr, xpp.p, xt.act != 0, xt.cr, xt.p);
+            const F Mint = new_flux<F>(xp, e1p - e1Lp, X, Y, rf, grf, fcf);
+            const F Yd = upwind_diff<F>(yp.f, yp.q, ypp.act != 0, ypp.f, ypp.q, yt.act != 0, yt.f, yt.q);
+            const F Xd = upwind_diff<F>(yp.cr, yp.p, yl_act != 0, yl_cr, yl_p, yr_act != 0, yr_cr, yr_p);
+            const F Nint = new_flux<F>(yp, e1p - e1pp, Yd, Xd, rf, grf, fcf);
             const bool xf_here = col_xf && rr < ny;
-            const bool yf_here = col_cell;
-            if (xf_here) {
-                if (col_xint) {
-                    if (xp.act) {
-                        const F X = upwind_diff<F>(xp.f, xp.q, xl_act != 0, xl_f, xl_q, xr_act != 0, xr_f, xr_q);
-                        const F Y = upwind_diff<F>(xp.cr, xp.p, xpp.act != 0, xpp.cr, xpp.p, xt.act != 0, xt.cr, xt.p);
-                        Mnew = new_flux<F>(xp, e1p - e1Lp, X, Y, rf, grf, fcf);
-                    }
-                } else if (root) {
-                    Mnew = (F)((c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
-                                        : (d.bc[1] ? 0.0 : radiate(d.g, eps, HLp, e1Lp, 1.0)));
+            const bool yf_int = col_cell && rr >= 1 && rr <= ny - 1;
+            F Mnew = (xp.act != 0) ? Mint : F(0);        // xp.act implies an interior face
+            F Nnew = (yp.act != 0) ? Nint : F(0);
+            if (root) {
+                const double mb = (c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
+                                           : (d.bc[1] ? 0.0 : radiate(d.g, eps, HLp, e1Lp, 1.0));
+                const double nbv = (rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
+                                             : (d.bc[3] ? 0.0 : radiate(d.g, eps, Hpp, e1pp, 1.0));
+                if (xf_here && !col_xint) Mnew = (F)mb;
+                if (col_cell && !(rr >= 1 && rr <= ny - 1)) Nnew = (F)nbv;
+            }
+            if (out_lane) {
+                if (xf_here && (col_xint || root)) *reinterpret_cast<F *>(Mo_a + ofs(rr) * (uint32_t)sizeof(F)) = Mnew;
+                if (col_cell && (yf_int || root)) *reinterpret_cast<F *>(No_a + ofs(rr) * (uint32_t)sizeof(F)) = Nnew;
+                if (col_cell && rr < ny) {
+                    *reinterpret_cast<double *>(Eo_a + ofs(rr) * (uint32_t)sizeof(double)) = e1p;
+                    const F v = (F)((Hp > 0.0) ? e1p : Hp + e1p);
+                    if (v > Zp) *reinterpret_cast<F *>(Z_a + ofs(rr) * (uint32_t)sizeof(F)) = v;
+                    quiet = quiet && !(Hp + e1p > eps);
                 }
-                if (col_xint || root) Mo[c + P * rr] = Mnew;
+                quiet = quiet && (Mnew == F(0)) && (Nnew == F(0));
+                if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew);
             }
-            if (yf_here) {
-                if (rr >= 1 && rr <= ny - 1) {
-                    if (yp.act) {
-                        const F Yd = upwind_diff<F>(yp.f, yp.q, ypp.act != 0, ypp.f, ypp.q, yt.act != 0, yt.f, yt.q);
-                        const F Xd = upwind_diff<F>(yp.cr, yp.p, yl_act != 0, yl_cr, yl_p, yr_act != 0, yr_cr, yr_p);
-                        Nnew = new_flux<F>(yp, e1p - e1pp, Yd, Xd, rf, grf, fcf);
-                    }
-                } else if (root) {
-                    Nnew = (F)((rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
-                                         : (d.bc[3] ? 0.0 : radiate(d.g, eps, Hpp, e1pp, 1.0)));
-                }
-                if ((rr >= 1 && rr <= ny - 1) || root) No[c + P * rr] = Nnew;
-            }
-            if (col_cell && rr < ny) {
-                Eo[c + P * rr] = e1p;
-                const F v = (F)((Hp > 0.0) ? e1p : Hp + e1p);
-                const int zc = c + P * rr;
-                if (v > Z[zc]) Z[zc] = v;
-                quiet = quiet && !(Hp + e1p > eps);
-            }
-            quiet = quiet && (Mnew == F(0)) && (Nnew == F(0));
-            if (has_child)
-                inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_here && rr >= 1 && rr <= ny - 1, Mnew, Nnew);
         }
 
         // Roll the window.
@@ -336,6 +346,7 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
         Hpp = Hp; Hp = H_t; HLp = HL;
         Mxp = Mx_t; MxRp = MxR_t;
         Ny_t = Ny_t1; NyL_t = NyL_t1;
+        Zp = Z_t;
     }
 
     // Quiescence history of the tile: bit1 <- bit0, bit0 <- this step.
@@ -348,10 +359,8 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
 }
 
 // ---------------------------------------------------------------------------
-// Active tiles of the coming step, in tile order, by one workgroup of 1024
-// threads: in each round every thread tests one tile (its 9 flag bytes are
-// loaded together), a block-wide exclusive scan places the round's active
-// tiles after those of the previous rounds.
+// Active tiles of the coming step.  A tile is tested with its 9 flag bytes
+// loaded together.
 __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_active)
 {
     if (all_active) return 1;
@@ -374,41 +383,43 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
     return (acc & 3u) == 3u ? 0 : 1;
 }
 
-__global__ __launch_bounds__(1024) void k_active(DomainDev d, int all_active)
+// One thread per tile, 256 tiles per workgroup: a block-wide scan orders the
+// block's active tiles and one atomic reserves their place in the list of
+// step parity b (the list keeps each block's tiles together and in order).
+// The counter of the other parity, read by nobody during this step, is reset
+// for the next one, so no memset is needed between steps.
+__global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)
 {
-    __shared__ int wsum[16];
-    const int n = d.ntiles;
+    __shared__ int wsum[4];
+    __shared__ int base;
     const int tid = (int)threadIdx.x;
+    const int g = (int)blockIdx.x * 256 + tid;
+    const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
     const int lane = tid & 63, w = tid >> 6;
-    int base = 0;
-    for (int r0 = 0; r0 < n; r0 += 1024) {
-        const int g = r0 + tid;
-        const int a = (g < n) ? tile_active(d, g, all_active) : 0;
-        int incl = a;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
-        }
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int k = 0; k < 16; ++k) {
-            const int s = wsum[k];
-            before += (k < w) ? s : 0;
-            total += s;
-        }
-        if (a) d.list[base + before + incl - 1] = g;
-        base += total;
-        __syncthreads();
+    int incl = a;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
     }
-    if (tid == 0) *d.count = base;
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int s = wsum[k];
+        before += (k < w) ? s : 0;
+        total += s;
+    }
+    if (tid == 0) base = total ? atomicAdd(&d.count[b], total) : 0;
+    if (blockIdx.x == 0 && tid == 0) d.count[b ^ 1] = 0;
+    __syncthreads();
+    if (a) d.list[base + before + incl - 1] = g;
 }
 
 }  // namespace
 
-hipError_t launch_active(const DomainDev &d, int all_active, hipStream_t s)
+hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_active, dim3(1), dim3(1024), 0, s, d, all_active);
+    hipLaunchKernelGGL(k_active, dim3((d.ntiles + 255) / 256), dim3(256), 0, s, d, b, all_active);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rti.h"
+#include "rti.h"
 #include "rti_internal.h"
 
 namespace {
@@ -138,13 +138,14 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
             p.ox = P.ox + (double)L.off_i * P.dx;
             p.oy = P.oy + (double)L.off_j * P.dx;
         }
-        const long long pitch = (long long)align_up((size_t)L.nx + 1, 32);
-        if (pitch * (long long)(L.ny + 1) >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
+        // Zero-padded layout (see LevelDev): pitch >= nx + 64, ny + 6 rows.
+        const long long pitch = (long long)align_up((size_t)L.nx + 64, 32);
+        if (pitch * (long long)(L.ny + 6) * 8 >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
         p.pitch = (int)pitch;
-        p.eta_bytes = align_up((size_t)pitch * (size_t)L.ny * sizeof(double), kAlign);
-        p.cells_bytes = align_up((size_t)pitch * (size_t)L.ny * plan.elem, kAlign);
+        p.eta_bytes = align_up((size_t)pitch * (size_t)(L.ny + 6) * sizeof(double), kAlign);
+        p.cells_bytes = align_up((size_t)pitch * (size_t)(L.ny + 6) * plan.elem, kAlign);
         p.xf_bytes = p.cells_bytes;
-        p.yf_bytes = align_up((size_t)pitch * (size_t)(L.ny + 1) * plan.elem, kAlign);
+        p.yf_bytes = p.cells_bytes;
     }
     for (int a = 1; a < d->n_levels; ++a) {
         for (int b = a + 1; b < d->n_levels; ++b) {
@@ -203,7 +204,7 @@ struct rti_domain {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     void *mem = nullptr;                 // base of the carved memory
     bool owns_mem = false;
-    int *ctrl = nullptr;                 // [0] active tile count, [1] divergence flag
+    int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag
     uint8_t *tinfo = nullptr;
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;
@@ -222,14 +223,17 @@ int carve(rti_domain *D)
     for (int k = 0; k < (int)D->plan.lv.size(); ++k) {
         const LevelPlan &pl = D->plan.lv[k];
         LevelDev &L = D->dev.lv[k];
-        L.eta[0] = reinterpret_cast<double *>(take(pl.eta_bytes));
-        L.eta[1] = reinterpret_cast<double *>(take(pl.eta_bytes));
-        L.h = take(pl.cells_bytes);
-        L.zmax = take(pl.cells_bytes);
-        L.M[0] = take(pl.xf_bytes);
-        L.M[1] = take(pl.xf_bytes);
-        L.N[0] = take(pl.yf_bytes);
-        L.N[1] = take(pl.yf_bytes);
+        // base pointer = cell (0,0): 3 padding rows and 2 padding columns in
+        const size_t in = (size_t)3 * pl.pitch + 2;
+        auto based = [&](size_t bytes, size_t elem) { return take(bytes) + in * elem; };
+        L.eta[0] = reinterpret_cast<double *>(based(pl.eta_bytes, sizeof(double)));
+        L.eta[1] = reinterpret_cast<double *>(based(pl.eta_bytes, sizeof(double)));
+        L.h = based(pl.cells_bytes, D->plan.elem);
+        L.zmax = based(pl.cells_bytes, D->plan.elem);
+        L.M[0] = based(pl.xf_bytes, D->plan.elem);
+        L.M[1] = based(pl.xf_bytes, D->plan.elem);
+        L.N[0] = based(pl.yf_bytes, D->plan.elem);
+        L.N[1] = based(pl.yf_bytes, D->plan.elem);
     }
     const size_t nt = (size_t)D->plan.ntiles;
     D->tinfo = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
@@ -237,7 +241,7 @@ int carve(rti_domain *D)
     D->dev.tflag = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.list = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
     D->ctrl = reinterpret_cast<int *>(take(kAlign));
-    D->dev.count = D->ctrl;         // ctrl[0]: active tiles
+    D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity
     return RTI_OK;
 }
 
@@ -310,8 +314,10 @@ int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &
     for (int b = 0; b < 2; ++b) {
         int rc = put_rows(D, L.eta[b], p.pitch, eta.data(), p.nx, p.ny);
         if (rc) return rc;
-        HIP_TRY(hipMemsetAsync(L.M[b], 0, p.xf_bytes, D->stream));
-        HIP_TRY(hipMemsetAsync(L.N[b], 0, p.yf_bytes, D->stream));
+        // whole padded allocations (their base pointers are 3 rows + 2 columns in)
+        const size_t in = ((size_t)3 * p.pitch + 2) * D->plan.elem;
+        HIP_TRY(hipMemsetAsync(static_cast<char *>(L.M[b]) - in, 0, p.xf_bytes, D->stream));
+        HIP_TRY(hipMemsetAsync(static_cast<char *>(L.N[b]) - in, 0, p.yf_bytes, D->stream));
     }
     int rc = put_rows_b(D, L.zmax, p.pitch, z.data(), p.nx, p.ny);
     if (rc) return rc;
@@ -328,7 +334,7 @@ int launch_step(rti_domain *D, int b, hipStream_t s)
         HIP_TRY(launch_momentum(D->dev, b, s));
         HIP_TRY(launch_jnq(D->dev, b, s));
     } else {
-        HIP_TRY(launch_active(D->dev, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
+        HIP_TRY(launch_active(D->dev, b, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
         HIP_TRY(launch_fused(D->dev, b, s));
     }
     return RTI_OK;
@@ -345,7 +351,8 @@ int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
         return RTI_OK;
     }
     int n = 0;
-    HIP_TRY(hipMemcpyAsync(&n, D->ctrl, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    // the last step read buffer cur^1, so its list was counted in ctrl[cur^1]
+    HIP_TRY(hipMemcpyAsync(&n, D->ctrl + (D->cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, D->stream));
     HIP_TRY(hipStreamSynchronize(D->stream));
     if (D->steps == 0) n = D->dev.ntiles;
     std::vector<int32_t> list(n);
@@ -506,10 +513,13 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             const LevelPlan &p = plan.lv[k];
             rc = put_rows_b(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
             if (rc) { rti_domain_destroy(D); return rc; }
-            std::vector<double> eta((size_t)p.nx * p.ny);
-            const double *h = desc->levels[k].h;
+            // the lake at rest on the depth as the kernels see it (rounded to FP32 in FP32-bulk)
+            std::vector<double> h(desc->levels[k].h, desc->levels[k].h + (size_t)p.nx * p.ny);
+            if (plan.elem == sizeof(float))
+                for (double &v : h) v = (double)(float)v;
+            std::vector<double> eta(h.size());
             for (size_t c = 0; c < eta.size(); ++c) eta[c] = (h[c] > 0.0) ? 0.0 : -h[c];
-            rc = install_initial(D, k, h, eta);
+            rc = install_initial(D, k, h.data(), eta);
             if (rc) { rti_domain_destroy(D); return rc; }
         }
         *out = D;
@@ -641,10 +651,10 @@ int rti_run(rti_domain *D, double t_end)
         int rc = rti_step(D, target - D->steps);
         if (rc) return rc;
     }
-    HIP_TRY(launch_zero_int(D->ctrl + 1, 1, D->stream));
-    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl + 1, D->stream));
+    HIP_TRY(launch_zero_int(D->ctrl + 2, 1, D->stream));
+    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl + 2, D->stream));
     int flag = 0;
-    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl + 1, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, D->stream));
     HIP_TRY(hipStreamSynchronize(D->stream));
     if (flag) {
         D->diverged = true;
@@ -743,7 +753,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
             kinds[0] = K_MASS; kinds[1] = K_JNZ; kinds[2] = K_MOMENTUM; kinds[3] = K_JNQ;
             nk = 4;
         } else {
-            if (e == hipSuccess) e = launch_active(D->dev, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, D->stream);
+            if (e == hipSuccess) e = launch_active(D->dev, b, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, D->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
             if (e == hipSuccess) e = launch_fused(D->dev, b, D->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);

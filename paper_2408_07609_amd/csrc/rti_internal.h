@@ -12,7 +12,9 @@
 // writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
 // right); it streams up RTI_TH output rows (plus 3 rows of pipeline warm-up).
 #define RTI_TW 60
-#define RTI_TH 32
+#ifndef RTI_TH
+#define RTI_TH 8
+#endif
 
 // Static per-tile bits (host-computed at create).
 #define TI_PINNED 0x1u      // never skipped and never reported quiescent
@@ -20,8 +22,11 @@
 #define TI_EDGE 0x4u        // the tile's extended region meets the level's outer faces
 
 // One level on the device.  Every field of a level shares one row pitch P
-// (a multiple of 32 elements, >= nx + 1): cell (i,j), x-face (i,j) and
-// y-face (i,j) all live at element i + P*j of their array.  eta and the
+// (a multiple of 32 elements, >= nx + 64): cell (i,j), x-face (i,j) and
+// y-face (i,j) all live at element i + P*j of their array, counted from the
+// array's base pointer.  Each array is a zeroed allocation of P x (ny + 6)
+// elements whose base pointer is 3 rows and 2 columns in, so columns -2 ..
+// P-3 and rows -3 .. ny+2 can be read and hold 0 outside the level.  eta and the
 // fluxes are double-buffered; buffer b of a step is read, buffer b^1 written.
 // eta is always FP64; h, the maxima and the fluxes are FP64, or FP32 when the
 // domain runs in FP32-bulk precision (DomainDev::bulk32).
@@ -46,8 +51,8 @@ struct DomainDev {
     double eps, fc, g;                     // dry threshold, dt/2 g n^2, gravity
     const uint8_t *tinfo;                  // ntiles static bits (TI_*)
     uint8_t *tflag;                        // ntiles: bit0 quiescent after the last step, bit1 after the one before
-    int32_t *list;                         // ntiles: active tiles of the current step, in tile order
-    int32_t *count;                        // [0] number of active tiles
+    int32_t *list;                         // ntiles: active tiles of the current step
+    int32_t *count;                        // [b] number of active tiles of a step reading buffer b
     LevelDev lv[RTI_MAX_LEVELS_DEV];
 };
 
@@ -63,5 +68,5 @@ hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
-hipError_t launch_active(const DomainDev &d, int all_active, hipStream_t s);
+hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s);
 hipError_t launch_fused(const DomainDev &d, int b, hipStream_t s);

@@ -59,7 +59,8 @@ __device__ __forceinline__ double mbar_y(const View &v, int i, int j)
 }
 
 // x-momentum at interior x-face (i,j): M_new = ((1-F) M - Pr - A) / (1+F) with
-// Pr = (gr D)(eta_i - eta_{i-1}), A = r (X + Y), F = (fc sqrt(M^2+Nb^2)) / ((D D) cbrt D).
+// Pr = (gr D)(eta_i - eta_{i-1}), A = r (X + Y), F = fc sqrt(M^2+Nb^2) D^(-7/3)
+// (momentum_update); the quotients by depths use 1/D (over_depth).
 __device__ double xmom(const View &v, double eps, double r, double gr, double fc, int i, int j)
 {
     double D;
@@ -67,26 +68,26 @@ __device__ double xmom(const View &v, double eps, double r, double gr, double fc
     const int P = v.P;
     const double m = v.M[i + P * j];
     const double nb = nbar_x(v, i, j);
-    const double Pr = (gr * D) * (v.eta[i + P * j] - v.eta[(i - 1) + P * j]);
+
+    const double iD = recip(D);
 
     double Dm = 0.0, Dp = 0.0;
     const bool okm = (i - 1 >= 1) && xdepth(v, eps, i - 1, j, Dm);
     const bool okp = (i + 1 <= v.nx - 1) && xdepth(v, eps, i + 1, j, Dp);
     const double mm = okm ? v.M[(i - 1) + P * j] : 0.0;
     const double mp = okp ? v.M[(i + 1) + P * j] : 0.0;
-    const double X = upwind_diff(m, (m * m) / D, okm, mm, okm ? (mm * mm) / Dm : 0.0,
-                                 okp, mp, okp ? (mp * mp) / Dp : 0.0);
+    const double X = upwind_diff(m, over_depth(m, m, iD), okm, mm, okm ? over_depth(mm, mm, recip(Dm)) : 0.0,
+                                 okp, mp, okp ? over_depth(mp, mp, recip(Dp)) : 0.0);
 
     double Ds = 0.0, Dn = 0.0;
     const bool oks = (j - 1 >= 0) && xdepth(v, eps, i, j - 1, Ds);
     const bool okn = (j + 1 <= v.ny - 1) && xdepth(v, eps, i, j + 1, Dn);
     const double nbs = oks ? nbar_x(v, i, j - 1) : 0.0;
     const double nbn = okn ? nbar_x(v, i, j + 1) : 0.0;
-    const double Y = upwind_diff(nb, (m * nb) / D, oks, nbs, oks ? (v.M[i + P * (j - 1)] * nbs) / Ds : 0.0,
-                                 okn, nbn, okn ? (v.M[i + P * (j + 1)] * nbn) / Dn : 0.0);
-    const double A = r * (X + Y);
-    const double F = (fc * sqrt(m * m + nb * nb)) / ((D * D) * cbrt(D));
-    return (((1.0 - F) * m - Pr) - A) / (1.0 + F);
+    const double Y = upwind_diff(nb, over_depth(m, nb, iD), oks, nbs,
+                                 oks ? over_depth(v.M[i + P * (j - 1)], nbs, recip(Ds)) : 0.0, okn, nbn,
+                                 okn ? over_depth(v.M[i + P * (j + 1)], nbn, recip(Dn)) : 0.0);
+    return momentum_update(m, nb, D, v.eta[i + P * j] - v.eta[(i - 1) + P * j], X, Y, r, gr, fc);
 }
 
 // y-momentum at interior y-face (i,j): the mirror of xmom (x<->y, M<->N).
@@ -97,26 +98,26 @@ __device__ double ymom(const View &v, double eps, double r, double gr, double fc
     const int P = v.P;
     const double n = v.N[i + P * j];
     const double mb = mbar_y(v, i, j);
-    const double Pr = (gr * D) * (v.eta[i + P * j] - v.eta[i + P * (j - 1)]);
+
+    const double iD = recip(D);
 
     double Ds = 0.0, Dn = 0.0;
     const bool oks = (j - 1 >= 1) && ydepth(v, eps, i, j - 1, Ds);
     const bool okn = (j + 1 <= v.ny - 1) && ydepth(v, eps, i, j + 1, Dn);
     const double ns = oks ? v.N[i + P * (j - 1)] : 0.0;
     const double nn = okn ? v.N[i + P * (j + 1)] : 0.0;
-    const double Yd = upwind_diff(n, (n * n) / D, oks, ns, oks ? (ns * ns) / Ds : 0.0,
-                                  okn, nn, okn ? (nn * nn) / Dn : 0.0);
+    const double Yd = upwind_diff(n, over_depth(n, n, iD), oks, ns, oks ? over_depth(ns, ns, recip(Ds)) : 0.0,
+                                  okn, nn, okn ? over_depth(nn, nn, recip(Dn)) : 0.0);
 
     double Dw = 0.0, De = 0.0;
     const bool okw = (i - 1 >= 0) && ydepth(v, eps, i - 1, j, Dw);
     const bool oke = (i + 1 <= v.nx - 1) && ydepth(v, eps, i + 1, j, De);
     const double mbw = okw ? mbar_y(v, i - 1, j) : 0.0;
     const double mbe = oke ? mbar_y(v, i + 1, j) : 0.0;
-    const double Xd = upwind_diff(mb, (n * mb) / D, okw, mbw, okw ? (v.N[(i - 1) + P * j] * mbw) / Dw : 0.0,
-                                  oke, mbe, oke ? (v.N[(i + 1) + P * j] * mbe) / De : 0.0);
-    const double A = r * (Yd + Xd);
-    const double F = (fc * sqrt(n * n + mb * mb)) / ((D * D) * cbrt(D));
-    return (((1.0 - F) * n - Pr) - A) / (1.0 + F);
+    const double Xd = upwind_diff(mb, over_depth(n, mb, iD), okw, mbw,
+                                  okw ? over_depth(v.N[(i - 1) + P * j], mbw, recip(Dw)) : 0.0, oke, mbe,
+                                  oke ? over_depth(v.N[(i + 1) + P * j], mbe, recip(De)) : 0.0);
+    return momentum_update(n, mb, D, v.eta[i + P * j] - v.eta[i + P * (j - 1)], Yd, Xd, r, gr, fc);
 }
 
 // ---------------------------------------------------------------------------
