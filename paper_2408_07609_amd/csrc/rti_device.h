@@ -31,12 +31,17 @@ __device__ __forceinline__ bool face_depth(double ha, double ea, double hb, doub
 template <typename F>
 __device__ __forceinline__ F upwind_diff(F s, F v, bool okm, F sm, F vm, bool okp, F sp, F vp)
 {
-    const F behind = okm ? v - vm : F(0);
-    const F ahead = okp ? vp - v : F(0);
-    const F a = (okm & (sm > F(0))) ? vm : F(0);
-    const F c = (okp & (sp < F(0))) ? vp : F(0);
-    const F tie = (-a) + c;
-    return (s > F(0)) ? behind : ((s < F(0)) ? ahead : tie);
+    // One subtraction of selected operands: s > 0 takes v - vm, s < 0 takes
+    // vp - v, s == 0 takes c - a (c = vp if that face flows in, a = vm if that
+    // one does; c - a is exactly (-a) + c), and a missing neighbour gives 0 - 0.
+    const bool pos = s > F(0), neg = s < F(0);
+    const bool l_v = pos & okm;                              // lhs = v
+    const bool l_vp = (neg & okp) | (!pos & !neg & okp & (sp < F(0)));   // lhs = vp
+    const bool r_vm = l_v | (!pos & !neg & okm & (sm > F(0)));           // rhs = vm
+    const bool r_v = neg & okp;                              // rhs = v
+    const F lhs = l_v ? v : (l_vp ? vp : F(0));
+    const F rhs = r_vm ? vm : (r_v ? v : F(0));
+    return lhs - rhs;
 }
 
 // Open side of the root: flux = sign * (sqrt(g h) * eta) of the boundary cell;
@@ -63,17 +68,18 @@ __device__ __forceinline__ float recip(float x)
     return fmaf(r, e, r);
 }
 
-// x^(-1/3) for x > 0: a binary32 estimate 2^(-log2(x)/3) refined by Newton
-// steps of z <- z (4 - x z^3) / 3 (quadratic convergence: two steps take the
-// ~1e-7 estimate to binary64 rounding, one step suffices for binary32).
+// x^(-1/3) for x > 0: a binary32 estimate z = 2^(-log2(x)/3) (relative error
+// d below 1e-6), then one correction of second order.  With e = 1 - x z^3
+// (about -3d), the exact value is z (1 - e)^(-1/3) = z (1 + e/3 + 2e^2/9 +
+// O(e^3)); the dropped O(e^3) term is below 1e-17 relative, so the result is
+// within about 1.5 ulp of binary64.
 __device__ __forceinline__ double rcbrt(double x)
 {
-    double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)x));
-    for (int k = 0; k < 2; ++k) {
-        const double z3 = (z * z) * z;
-        z = (z * (4.0 - x * z3)) * (1.0 / 3.0);
-    }
-    return z;
+    const double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)x));
+    const double z3 = (z * z) * z;
+    const double e = fma(-x, z3, 1.0);
+    const double c = fma(e, 2.0 / 9.0, 1.0 / 3.0);
+    return fma(z * e, c, z);
 }
 __device__ __forceinline__ float rcbrt(float x)
 {
@@ -81,6 +87,22 @@ __device__ __forceinline__ float rcbrt(float x)
     const float z3 = (z * z) * z;
     return (z * (4.0f - x * z3)) * (1.0f / 3.0f);
 }
+
+// sqrt(x) for x >= 0 (0 for x = 0): the hardware reciprocal square root y
+// refined by one Goldschmidt step on (g, h) = (x y, y/2) and one residual
+// correction g += (x - g^2) h; within about 1 ulp of the rounded root.
+__device__ __forceinline__ double sqrt_nonneg(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return (x > 0.0) ? g : 0.0;
+}
+__device__ __forceinline__ float sqrt_nonneg(float x) { return sqrtf(x); }
 
 // Momentum flux quantity a*b/D given 1/D.
 template <typename F>
@@ -100,7 +122,7 @@ __device__ __forceinline__ F momentum_update(F f, F cr, F D, F de, F along, F cr
     const F z = rcbrt(D);
     const F z2 = z * z;
     const F z7 = (z2 * z2) * (z2 * z);
-    const F Fr = (fc * sqrt(f * f + cr * cr)) * z7;
+    const F Fr = (fc * sqrt_nonneg(f * f + cr * cr)) * z7;
     return (((F(1) - Fr) * f - Pr) - A) * recip(F(1) + Fr);
 }
 

@@ -31,6 +31,8 @@
 // no-op: its cells and faces and all that its stencil reads keep their values,
 // and both state buffers already hold them.  Dry land therefore costs no
 // bandwidth once it is quiet.
+#include <type_traits>
+
 #include "rti_device.h"
 #include "rti_internal.h"
 
@@ -38,10 +40,11 @@ namespace {
 using namespace rti_dev;
 
 // Value held by lane+1 (from_right) or lane-1 (from_left): wavefront-wide DPP
-// shifts (wave_shl:1 = 0x130, wave_shr:1 = 0x138); the lane without a source
-// receives 0.  Called only in wave-uniform control flow.
-__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+// shifts (wave_shl:1 = 0x130, wave_shr:1 = 0x138); with bound_ctrl set, the
+// lane without a source receives 0 (so no old value has to be set up).
+// Called only in wave-uniform control flow.
+__device__ __forceinline__ int dpp_right_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_left_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 
 __device__ __forceinline__ double from_right(double v)
 {
@@ -78,8 +81,9 @@ template <typename F>
 __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, double hb, double eb, double eps,
                                           F f, F cr)
 {
-    // Computed on every lane; an inactive face carries D = 1 (a safe value
-    // that is never used) and q = p = 0.
+    // Computed on every lane.  An inactive face carries D = 1 (a safe value)
+    // and q, p of that D; nothing reads them: neighbours test act first, and
+    // the face's own new flux is replaced by 0.
     FaceQ<F> o;
     double D;
     const bool act = face_depth(ha, ea, hb, eb, eps, D) & interior;
@@ -89,10 +93,22 @@ __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, 
     o.D = Df;
     o.f = f;
     o.cr = cr;
-    o.q = act ? over_depth(f, f, iD) : F(0);
-    o.p = act ? over_depth(f, cr, iD) : F(0);
+    o.q = over_depth(f, f, iD);
+    o.p = over_depth(f, cr, iD);
     return o;
 }
+
+// One row of the fused kernel's rolling window.
+template <typename F>
+struct RowW {
+    double E, H;        // raw eta and h of the row
+    F Mx, Ny;           // raw flux of the row's x-face and of its top y-face (j = row + 1)
+    F Z;                // maxima of the row before this step
+    double e1;          // new eta of the row
+    double e1L, HL;     // new eta and h of the cell on the left
+    F MxR, NyL;         // x-face flux on the right, top y-face flux on the left
+    FaceQ<F> x, y;      // the row's x-face and bottom y-face (j = row)
+};
 
 // New flux of an active face (momentum_update); de is the FP64 water-level
 // difference across the face.
@@ -216,18 +232,18 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     const bool out_lane = (lane >= 2) && (lane < 2 + RTI_TW);
 
     // Every array is padded with zeros: 2 columns on the left, at least 61 on
-    // the right of the last face, 3 rows below and 3 above; the padding is
+    // the right of the last face, 3 rows below and RTI_PD + 3 above; the padding is
     // never written.  So a lane can load any (c, row) of its tile without a
     // bounds test and gets exactly 0 outside the level.  Offsets are taken
     // from the start of the padded allocation (always >= 0), one 32-bit
     // element offset per row shared by every array.
-    const uint32_t pad = (uint32_t)(3 * P + 2);
+    const uint32_t pad = (uint32_t)(RTI_PAD_BOTTOM * P + 2);
     const char *Eb_a = reinterpret_cast<const char *>(Eb - pad);
     const char *Hh_a = reinterpret_cast<const char *>(Hh - pad);
     const char *Mb_a = reinterpret_cast<const char *>(Mb - pad);
     const char *Nb_a = reinterpret_cast<const char *>(Nb - pad);
-    const uint32_t u0 = (uint32_t)(x0 + lane);                    // element offset of (c, -3)
-    auto ofs = [&](int row) -> uint32_t { return u0 + (uint32_t)P * (uint32_t)(row + 3); };
+    const uint32_t u0 = (uint32_t)(x0 + lane);                    // element offset of (c, -RTI_PAD_BOTTOM)
+    auto ofs = [&](int row) -> uint32_t { return u0 + (uint32_t)P * (uint32_t)(row + RTI_PAD_BOTTOM); };
     auto ld_eta = [&](int row) -> double {
         return *reinterpret_cast<const double *>(Eb_a + ofs(row) * (uint32_t)sizeof(double));
     };
@@ -240,14 +256,6 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     const int t0 = y0 - 2;
     const int t1 = min(y0 + RTI_TH, ny + 1);   // last iteration; it writes row t1 - 1
 
-    // Rolling window (suffix p = row t-1, pp = row t-2).
-    F Ny_t = ld_yf(t0);
-    F NyL_t = from_left(Ny_t);
-    double e1p = 0.0, e1pp = 0.0, e1Lp = 0.0, Hp = 0.0, Hpp = 0.0, HLp = 0.0;
-    F Mxp = F(0), MxRp = F(0);
-    FaceQ<F> xp{}, xpp{}, yp{}, ypp{};
-    bool quiet = true;
-
     // Output arrays through the same padded offsets.
     char *Eo_a = reinterpret_cast<char *>(Eo - pad);
     char *Mo_a = reinterpret_cast<char *>(Mo - pad);
@@ -255,51 +263,61 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     char *Z_a = reinterpret_cast<char *>(Z - pad);
     auto ld_z = [&](int row) -> F { return *reinterpret_cast<const F *>(Z_a + ofs(row) * (uint32_t)sizeof(F)); };
 
-    // Memory pipeline: the raw row t+1 and the maxima of row t are loaded at
-    // the top of iteration t, so the loads have a whole row of arithmetic to
-    // arrive and the maxima update never waits on a load.
-    double E_n = ld_eta(t0), H_n = ld_h(t0);
-    F Mx_n = ld_xf(t0), Ny_n = ld_yf(t0 + 1);
-    F Zp = F(0);                                   // maxima of row t-1
+    // Rolling window of RTI_NS = RTI_PD + 3 rows: iteration t works on slot
+    // K = (t - t0) mod RTI_NS (row t); K-1 holds row t-1, K-2 row t-2, and
+    // K+RTI_PD receives the raw loads of row t+RTI_PD, which therefore have
+    // RTI_PD rows of arithmetic to arrive.  The loop is unrolled by RTI_NS so
+    // every slot index is a compile-time constant and rows rotate by renaming,
+    // not by copying registers.
+    constexpr int NS = RTI_NS;
+    RowW<F> w[NS] = {};
+    w[NS - 1].Ny = ld_yf(t0);                      // bottom face of the first row
+    w[NS - 1].NyL = from_left(w[NS - 1].Ny);
+#pragma unroll
+    for (int k = 0; k < RTI_PD; ++k) {
+        w[k].E = ld_eta(t0 + k);
+        w[k].H = ld_h(t0 + k);
+        w[k].Mx = ld_xf(t0 + k);
+        w[k].Ny = ld_yf(t0 + k + 1);
+    }
+    bool quiet = true;
 
-    for (int t = t0; t <= t1; ++t) {
-        const double E_t = E_n, H_t = H_n;
-        const F Mx_t = Mx_n, Ny_t1 = Ny_n;
-        F Z_t = F(0);
-        if (t < t1) {
-            E_n = ld_eta(t + 1);
-            H_n = ld_h(t + 1);
-            Mx_n = ld_xf(t + 1);
-            Ny_n = ld_yf(t + 2);
-        }
-        if (t >= y0) Z_t = ld_z(t);
+    auto do_row = [&](auto kc, int t) {
+        constexpr int K = decltype(kc)::value;
+        RowW<F> &cur = w[K];
+        const RowW<F> &p = w[(K + NS - 1) % NS];
+        const RowW<F> &pp = w[(K + NS - 2) % NS];
+        RowW<F> &nxt = w[(K + RTI_PD) % NS];
+        // Unconditional loads (the last iterations' are not used; row
+        // t1 + RTI_PD + 1 <= ny + RTI_PD + 2 is still padding): a load under a
+        // branch would make the compiler wait for every load in flight where
+        // the paths join.
+        nxt.E = ld_eta(t + RTI_PD);
+        nxt.H = ld_h(t + RTI_PD);
+        nxt.Mx = ld_xf(t + RTI_PD);
+        nxt.Ny = ld_yf(t + RTI_PD + 1);
+        cur.Z = ld_z(t);
         const bool row_cell = (t >= 0) && (t < ny);
 
         // Continuity of row t (Eq. 1, FP64), then the child ring overlay.
-        const F MxR_t = from_right(Mx_t);
-        double e1 = E_t - r * (((double)MxR_t - (double)Mx_t) + ((double)Ny_t1 - (double)Ny_t));
+        const double H_t = cur.H;
+        cur.MxR = from_right(cur.Mx);
+        double e1 = cur.E - r * (((double)cur.MxR - (double)cur.Mx) + ((double)cur.Ny - (double)p.Ny));
         e1 = (H_t + e1 < 0.0) ? -H_t : e1;
         e1 = (col_cell && row_cell) ? e1 : 0.0;
         if (has_child) {
             if (col_cell && row_cell) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
         }
+        cur.e1 = e1;
 
         // Face quantities: x-face c of row t, y-face c at j = t.
-        const double e1L = from_left(e1);
-        const double HL = from_left(H_t);
-        const F NyL_t1 = from_left(Ny_t1);
-        const F nb = F(0.25) * ((NyL_t + NyL_t1) + (Ny_t + Ny_t1));
-        const FaceQ<F> xt = face_q<F>(col_xint && row_cell, HL, e1L, H_t, e1, eps, Mx_t, nb);
-        const F mb = F(0.25) * ((Mxp + MxRp) + (Mx_t + MxR_t));
-        const FaceQ<F> yt = face_q<F>(col_cell && t >= 1 && t <= ny - 1, Hp, e1p, H_t, e1, eps, Ny_t, mb);
-
-        // Neighbours of row t-1 along x (wave-uniform).
-        const int xl_act = dpp_left_i(xp.act), xr_act = dpp_right_i(xp.act);
-        const F xl_f = from_left(xp.f), xr_f = from_right(xp.f);
-        const F xl_q = from_left(xp.q), xr_q = from_right(xp.q);
-        const int yl_act = dpp_left_i(yp.act), yr_act = dpp_right_i(yp.act);
-        const F yl_cr = from_left(yp.cr), yr_cr = from_right(yp.cr);
-        const F yl_p = from_left(yp.p), yr_p = from_right(yp.p);
+        cur.e1L = from_left(e1);
+        cur.HL = from_left(H_t);
+        cur.NyL = from_left(cur.Ny);
+        const F nb = F(0.25) * ((p.NyL + cur.NyL) + (p.Ny + cur.Ny));
+        cur.x = face_q<F>(col_xint && row_cell, cur.HL, cur.e1L, H_t, e1, eps, cur.Mx, nb);
+        const F mb = F(0.25) * ((p.Mx + p.MxR) + (cur.Mx + cur.MxR));
+        cur.y = face_q<F>(col_cell && t >= 1 && t <= ny - 1, p.H, p.e1, H_t, e1, eps, p.Ny, mb);
 
         // Momentum and outputs of row (x-faces, cells) / face (y-faces) rr = t-1.
         // The momentum of both faces is evaluated on every lane (inactive
@@ -307,46 +325,73 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
         // stores depend on the lane.
         const int rr = t - 1;
         if (rr >= y0 && rr <= ny) {
+            const FaceQ<F> &xp = p.x, &yp = p.y;
+            const int xl_act = dpp_left_i(xp.act), xr_act = dpp_right_i(xp.act);
+            const F xl_f = from_left(xp.f), xr_f = from_right(xp.f);
+            const F xl_q = from_left(xp.q), xr_q = from_right(xp.q);
+            const int yl_act = dpp_left_i(yp.act), yr_act = dpp_right_i(yp.act);
+            const F yl_cr = from_left(yp.cr), yr_cr = from_right(yp.cr);
+            const F yl_p = from_left(yp.p), yr_p = from_right(yp.p);
             const F X = upwind_diff<F>(xp.f, xp.q, xl_act != 0, xl_f, xl_q, xr_act != 0, xr_f, xr_q);
-            const F Y = upwind_diff<F>(xp.cr, xp.p, xpp.act != 0, xpp.cr, xpp.p, xt.act != 0, xt.cr, xt.p);
-            const F Mint = new_flux<F>(xp, e1p - e1Lp, X, Y, rf, grf, fcf);
-            const F Yd = upwind_diff<F>(yp.f, yp.q, ypp.act != 0, ypp.f, ypp.q, yt.act != 0, yt.f, yt.q);
+            const F Y = upwind_diff<F>(xp.cr, xp.p, pp.x.act != 0, pp.x.cr, pp.x.p, cur.x.act != 0, cur.x.cr, cur.x.p);
+            const F Mint = new_flux<F>(xp, p.e1 - p.e1L, X, Y, rf, grf, fcf);
+            const F Yd = upwind_diff<F>(yp.f, yp.q, pp.y.act != 0, pp.y.f, pp.y.q, cur.y.act != 0, cur.y.f, cur.y.q);
             const F Xd = upwind_diff<F>(yp.cr, yp.p, yl_act != 0, yl_cr, yl_p, yr_act != 0, yr_cr, yr_p);
-            const F Nint = new_flux<F>(yp, e1p - e1pp, Yd, Xd, rf, grf, fcf);
+            const F Nint = new_flux<F>(yp, p.e1 - pp.e1, Yd, Xd, rf, grf, fcf);
             const bool xf_here = col_xf && rr < ny;
             const bool yf_int = col_cell && rr >= 1 && rr <= ny - 1;
             F Mnew = (xp.act != 0) ? Mint : F(0);        // xp.act implies an interior face
             F Nnew = (yp.act != 0) ? Nint : F(0);
             if (root) {
-                const double mb = (c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
-                                           : (d.bc[1] ? 0.0 : radiate(d.g, eps, HLp, e1Lp, 1.0));
-                const double nbv = (rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, Hp, e1p, -1.0))
-                                             : (d.bc[3] ? 0.0 : radiate(d.g, eps, Hpp, e1pp, 1.0));
-                if (xf_here && !col_xint) Mnew = (F)mb;
+                const double mbv = (c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, p.H, p.e1, -1.0))
+                                            : (d.bc[1] ? 0.0 : radiate(d.g, eps, p.HL, p.e1L, 1.0));
+                const double nbv = (rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, p.H, p.e1, -1.0))
+                                             : (d.bc[3] ? 0.0 : radiate(d.g, eps, pp.H, pp.e1, 1.0));
+                if (xf_here && !col_xint) Mnew = (F)mbv;
                 if (col_cell && !(rr >= 1 && rr <= ny - 1)) Nnew = (F)nbv;
             }
             if (out_lane) {
                 if (xf_here && (col_xint || root)) *reinterpret_cast<F *>(Mo_a + ofs(rr) * (uint32_t)sizeof(F)) = Mnew;
                 if (col_cell && (yf_int || root)) *reinterpret_cast<F *>(No_a + ofs(rr) * (uint32_t)sizeof(F)) = Nnew;
                 if (col_cell && rr < ny) {
-                    *reinterpret_cast<double *>(Eo_a + ofs(rr) * (uint32_t)sizeof(double)) = e1p;
-                    const F v = (F)((Hp > 0.0) ? e1p : Hp + e1p);
-                    if (v > Zp) *reinterpret_cast<F *>(Z_a + ofs(rr) * (uint32_t)sizeof(F)) = v;
-                    quiet = quiet && !(Hp + e1p > eps);
+                    *reinterpret_cast<double *>(Eo_a + ofs(rr) * (uint32_t)sizeof(double)) = p.e1;
+                    const F v = (F)((p.H > 0.0) ? p.e1 : p.H + p.e1);
+                    if (v > p.Z) *reinterpret_cast<F *>(Z_a + ofs(rr) * (uint32_t)sizeof(F)) = v;
+                    quiet = quiet && !(p.H + p.e1 > eps);
                 }
                 quiet = quiet && (Mnew == F(0)) && (Nnew == F(0));
                 if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew);
             }
         }
+    };
 
-        // Roll the window.
-        xpp = xp; xp = xt;
-        ypp = yp; yp = yt;
-        e1pp = e1p; e1p = e1; e1Lp = e1L;
-        Hpp = Hp; Hp = H_t; HLp = HL;
-        Mxp = Mx_t; MxRp = MxR_t;
-        Ny_t = Ny_t1; NyL_t = NyL_t1;
-        Zp = Z_t;
+    for (int t = t0;; t += NS) {
+#define RTI_ROW(K)                                              \
+        do_row(std::integral_constant<int, (K)>{}, t + (K));    \
+        if (t + (K) + 1 > t1) break;
+        RTI_ROW(0)
+        RTI_ROW(1)
+        RTI_ROW(2)
+        RTI_ROW(3)
+#if RTI_NS > 4
+        RTI_ROW(4)
+#endif
+#if RTI_NS > 5
+        RTI_ROW(5)
+#endif
+#if RTI_NS > 6
+        RTI_ROW(6)
+#endif
+#if RTI_NS > 7
+        RTI_ROW(7)
+#endif
+#if RTI_NS > 8
+        RTI_ROW(8)
+#endif
+#if RTI_NS > 9
+#error "RTI_PD above 6 is not unrolled"
+#endif
+#undef RTI_ROW
     }
 
     // Quiescence history of the tile: bit1 <- bit0, bit0 <- this step.

@@ -138,12 +138,13 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
             p.ox = P.ox + (double)L.off_i * P.dx;
             p.oy = P.oy + (double)L.off_j * P.dx;
         }
-        // Zero-padded layout (see LevelDev): pitch >= nx + 64, ny + 6 rows.
+        // Zero-padded layout (see LevelDev): pitch >= nx + 64, RTI_PAD_BOTTOM + ny + RTI_PAD_TOP rows.
+        const long long rows = (long long)RTI_PAD_BOTTOM + L.ny + RTI_PAD_TOP;
         const long long pitch = (long long)align_up((size_t)L.nx + 64, 32);
-        if (pitch * (long long)(L.ny + 6) * 8 >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
+        if (pitch * rows * 8 >= (1LL << 31)) return fail(RTI_EINVAL, "level %d too large", k);
         p.pitch = (int)pitch;
-        p.eta_bytes = align_up((size_t)pitch * (size_t)(L.ny + 6) * sizeof(double), kAlign);
-        p.cells_bytes = align_up((size_t)pitch * (size_t)(L.ny + 6) * plan.elem, kAlign);
+        p.eta_bytes = align_up((size_t)pitch * (size_t)rows * sizeof(double), kAlign);
+        p.cells_bytes = align_up((size_t)pitch * (size_t)rows * plan.elem, kAlign);
         p.xf_bytes = p.cells_bytes;
         p.yf_bytes = p.cells_bytes;
     }
@@ -223,8 +224,8 @@ int carve(rti_domain *D)
     for (int k = 0; k < (int)D->plan.lv.size(); ++k) {
         const LevelPlan &pl = D->plan.lv[k];
         LevelDev &L = D->dev.lv[k];
-        // base pointer = cell (0,0): 3 padding rows and 2 padding columns in
-        const size_t in = (size_t)3 * pl.pitch + 2;
+        // base pointer = cell (0,0): RTI_PAD_BOTTOM padding rows and 2 padding columns in
+        const size_t in = (size_t)RTI_PAD_BOTTOM * pl.pitch + 2;
         auto based = [&](size_t bytes, size_t elem) { return take(bytes) + in * elem; };
         L.eta[0] = reinterpret_cast<double *>(based(pl.eta_bytes, sizeof(double)));
         L.eta[1] = reinterpret_cast<double *>(based(pl.eta_bytes, sizeof(double)));
@@ -314,8 +315,8 @@ int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &
     for (int b = 0; b < 2; ++b) {
         int rc = put_rows(D, L.eta[b], p.pitch, eta.data(), p.nx, p.ny);
         if (rc) return rc;
-        // whole padded allocations (their base pointers are 3 rows + 2 columns in)
-        const size_t in = ((size_t)3 * p.pitch + 2) * D->plan.elem;
+        // whole padded allocations (their base pointers are RTI_PAD_BOTTOM rows + 2 columns in)
+        const size_t in = ((size_t)RTI_PAD_BOTTOM * p.pitch + 2) * D->plan.elem;
         HIP_TRY(hipMemsetAsync(static_cast<char *>(L.M[b]) - in, 0, p.xf_bytes, D->stream));
         HIP_TRY(hipMemsetAsync(static_cast<char *>(L.N[b]) - in, 0, p.yf_bytes, D->stream));
     }

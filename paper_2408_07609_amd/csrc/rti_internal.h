@@ -11,10 +11,23 @@
 // Tile of the fused kernel: one wavefront of 64 lanes covers 64 columns and
 // writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
 // right); it streams up RTI_TH output rows (plus 3 rows of pipeline warm-up).
+// Short tiles give many wavefronts (the launch drains evenly and many loads
+// are in flight); 6 rows measured best on gfx950 with RTI_PD = 2.
 #define RTI_TW 60
 #ifndef RTI_TH
-#define RTI_TH 8
+#define RTI_TH 6
 #endif
+// Rows of loads the fused kernel keeps in flight ahead of the row it computes,
+// and the rows of its rolling window (rows t-2 .. t+RTI_PD).  2 still fits
+// 3 wavefronts per SIMD (<= 168 VGPRs); deeper prefetch drops to 2.
+#ifndef RTI_PD
+#define RTI_PD 2
+#endif
+#define RTI_NS (RTI_PD + 3)
+// Zero rows above the last row of every array (the prefetch reads up to row
+// ny + RTI_PD + 2) and below row 0 (the warm-up reads down to row -3).
+#define RTI_PAD_TOP (RTI_PD + 3)
+#define RTI_PAD_BOTTOM 3
 
 // Static per-tile bits (host-computed at create).
 #define TI_PINNED 0x1u      // never skipped and never reported quiescent
@@ -24,9 +37,11 @@
 // One level on the device.  Every field of a level shares one row pitch P
 // (a multiple of 32 elements, >= nx + 64): cell (i,j), x-face (i,j) and
 // y-face (i,j) all live at element i + P*j of their array, counted from the
-// array's base pointer.  Each array is a zeroed allocation of P x (ny + 6)
-// elements whose base pointer is 3 rows and 2 columns in, so columns -2 ..
-// P-3 and rows -3 .. ny+2 can be read and hold 0 outside the level.  eta and the
+// array's base pointer.  Each array is a zeroed allocation of
+// P x (RTI_PAD_BOTTOM + ny + RTI_PAD_TOP) elements whose base pointer is
+// RTI_PAD_BOTTOM rows and 2 columns in, so columns -2 .. P-3 and rows
+// -RTI_PAD_BOTTOM .. ny + RTI_PAD_TOP - 1 can be read and hold 0 outside the
+// level.  eta and the
 // fluxes are double-buffered; buffer b of a step is read, buffer b^1 written.
 // eta is always FP64; h, the maxima and the fluxes are FP64, or FP32 when the
 // domain runs in FP32-bulk precision (DomainDev::bulk32).
