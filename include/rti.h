@@ -72,6 +72,9 @@ enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
 #define RTI_FLAG_NO_ACTIVE   0x2u   /* compute every tile; do not skip quiescent dry tiles */
 #define RTI_FLAG_PHASED      0x4u   /* one kernel per phase (mass, ring mean, momentum, edge fluxes)
                                        instead of the fused tile kernel; for comparison */
+#define RTI_FLAG_PERSISTENT  0x8u   /* launch the fused kernel with a fixed grid of resident
+                                       wavefronts that loop over the active tiles, instead of one
+                                       workgroup per tile (also a flag of rti_batch_create) */
 #define RTI_MAX_LEVELS 16
 
 /* One nest level.  Level 0 is the root (parent = -1); every other level names
@@ -184,9 +187,64 @@ int rti_profile(rti_domain *dom, int64_t nsteps, double *ms, const char **names,
  * tile counts as computed.  Synchronises. */
 int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *active_cells);
 
+/* Tile shape of the fused kernel.  A tile is 60 columns wide and `rows` rows
+ * high, rows in [RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX] (default
+ * RTI_TILE_ROWS_DEFAULT).  The tile shape changes only the work decomposition:
+ * results are bitwise the same for every height.  Setting it synchronises,
+ * rebuilds the tile tables and forgets the quiescence history (the next two
+ * steps compute every tile). */
+#define RTI_TILE_ROWS_MIN 4
+#define RTI_TILE_ROWS_MAX 64
+#define RTI_TILE_ROWS_DEFAULT 6
+int rti_domain_set_tile_rows(rti_domain *dom, int32_t rows);
+int rti_domain_tile_rows(const rti_domain *dom, int32_t *rows);
+
+/* Autotuner of the tile shape: for each candidate height (4, 5, 6, 8, 10, 12,
+ * 16, 24), run 2 untimed steps and then nsteps timed steps from the domain's
+ * current state, keep the fastest height, and restore the state, the maxima
+ * and the step count exactly as they were.  nsteps >= 1.  *rows_out (may be
+ * NULL) receives the height chosen; ms_out (may be NULL) the average step
+ * time [ms] at that height.  Allocates a device snapshot of the state for the
+ * duration of the call; synchronises. */
+int rti_domain_autotune(rti_domain *dom, int32_t nsteps, int32_t *rows_out, double *ms_out);
+
 /* Free the domain's device memory (when the library allocated it), its
- * graphs and the handle.  NULL is a no-op.  Synchronises first. */
+ * graphs and the handle.  NULL is a no-op.  Synchronises first.  A domain
+ * still in a batch is removed from it first. */
 void rti_domain_destroy(rti_domain *dom);
+
+/* ---------------------------------------------------------------------------
+ * Batches: several domains stepped together, one active-tile launch and one
+ * fused launch per step over a global table of every member's tiles (uneven
+ * sizes, level counts and tile heights mixed).  Each member keeps its own
+ * state, parity and maxima; a member's results are bitwise the ones it gets
+ * stepped alone.  Members must share the device, the precision and the
+ * stream given here (hip_stream, borrowed), may not use RTI_FLAG_PHASED, and
+ * belong to at most one batch.  While a domain is in a batch it is stepped
+ * only through the batch (rti_step and rti_run on it return RTI_ESTATE);
+ * reading its state, maxima and step count works as usual.  Members may be
+ * added and removed between batch steps (continuous batching: a member added
+ * later simply starts from its own state).  flags: RTI_FLAG_NO_GRAPH,
+ * RTI_FLAG_NO_ACTIVE, RTI_FLAG_PERSISTENT. */
+typedef struct rti_batch rti_batch;     /* opaque */
+
+int rti_batch_create(rti_domain *const *members, int32_t n, void *hip_stream, uint32_t flags, rti_batch **out);
+int rti_batch_add(rti_batch *batch, rti_domain *dom);
+int rti_batch_remove(rti_batch *batch, rti_domain *dom);
+int rti_batch_size(const rti_batch *batch, int32_t *n);
+
+/* Enqueue nsteps steps of every member (asynchronous). */
+int rti_batch_step(rti_batch *batch, int64_t nsteps);
+int rti_batch_sync(rti_batch *batch);
+
+/* Time nsteps batch steps launched one by one (advances every member):
+ * average fused-kernel and active-list-kernel durations per launch [ms] and
+ * the average number of cells in the tiles computed per step.  Synchronises. */
+int rti_batch_profile(rti_batch *batch, int64_t nsteps, double *fused_ms, double *active_ms, double *active_cells);
+
+/* Free the batch's tables and graphs; the members stay valid (and can be
+ * stepped alone again).  NULL is a no-op.  Synchronises first. */
+void rti_batch_destroy(rti_batch *batch);
 
 const char *rti_last_error(void);
 const char *rti_strerror(int code);

@@ -6,8 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("rti_kernels.hip", "rti_fused.hip", "rti_host.cpp")]
-HEADERS = [os.path.join(HERE, "csrc", n) for n in ("rti_internal.h", "rti_device.h")] + [os.path.join(ROOT, "include", "rti.h")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("rti_kernels.hip", "rti_fused.hip", "rti_host.cpp", "rti_batch.cpp")]
+HEADERS = [os.path.join(HERE, "csrc", n) for n in ("rti_internal.h", "rti_device.h", "rti_runtime.h")] + [os.path.join(ROOT, "include", "rti.h")]
 LIB = os.path.join(HERE, "_build", "librti.so")
 
 HIPCC_FLAGS = [

@@ -192,24 +192,16 @@ __device__ __forceinline__ int level_of_tile(const DomainDev &d, int g)
     return l;
 }
 
+// One tile g of domain d: read buffer b, write buffer b^1 (paper Eqs. 1-3
+// and the nest exchanges of Sec. IV-C for the tile's cells and faces).
 template <typename F>
-__global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
+__device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
 {
-    // Active tile of this workgroup.  Workgroups go to the 8 XCDs round-robin;
-    // XCD x receives the x-th contiguous slice of the (row-ordered) tile list,
-    // so the halo rows and columns a tile shares with its neighbours sit in
-    // the same L2.
-    const int n_active = d.count[b];
-    const int per = (n_active + 7) >> 3;
-    const int slot = (int)(blockIdx.x >> 3);
-    const int pos = (int)(blockIdx.x & 7) * per + slot;
-    if (slot >= per || pos >= n_active) return;
-    const int g = d.list[pos];
     const int l = level_of_tile(d, g);
     const LevelDev &L = d.lv[l];
     const int tl = g - L.tile_base;
     const int x0 = (tl % L.tiles_x) * RTI_TW;
-    const int y0 = (tl / L.tiles_x) * RTI_TH;
+    const int y0 = (tl / L.tiles_x) * d.th;
     const uint8_t info = d.tinfo[g];
     const bool has_child = (info & TI_CHILD) != 0;
     const bool root = (l == 0);
@@ -254,7 +246,7 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     auto ld_yf = [&](int row) -> F { return *reinterpret_cast<const F *>(Nb_a + ofs(row) * (uint32_t)sizeof(F)); };
 
     const int t0 = y0 - 2;
-    const int t1 = min(y0 + RTI_TH, ny + 1);   // last iteration; it writes row t1 - 1
+    const int t1 = min(y0 + d.th, ny + 1);     // last iteration; it writes row t1 - 1
 
     // Output arrays through the same padded offsets.
     char *Eo_a = reinterpret_cast<char *>(Eo - pad);
@@ -403,6 +395,62 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
     }
 }
 
+// Position in the active list of workgroup w's i-th tile.  Workgroups go to
+// the 8 XCDs round-robin; XCD x works through the x-th contiguous slice of the
+// (row-ordered) list, so the halo rows and columns a tile shares with its
+// neighbours sit in the same L2.  A grid smaller than the list makes every
+// workgroup loop over several tiles (a persistent grid); the loop bound is
+// uniform, so every wavefront reaches the exit.
+__device__ __forceinline__ int slice_pos(int n_active, int slot)
+{
+    const int per = (n_active + 7) >> 3;
+    if (slot >= per) return -1;
+    const int pos = (int)(blockIdx.x & 7) * per + slot;
+    return pos < n_active ? pos : -1;
+}
+
+// One workgroup per active tile.
+template <typename F>
+__global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
+{
+    const int pos = slice_pos(d.count[b], (int)(blockIdx.x >> 3));
+    if (pos >= 0) fused_tile<F>(d, b, d.list[pos]);
+}
+
+// A persistent grid: every workgroup loops over tiles.  (The loop costs the
+// register allocator a few registers; it is held to 3 wavefronts per SIMD.)
+template <typename F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_loop(DomainDev d, int b)
+{
+    const int n_active = d.count[b];
+    for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
+        const int pos = slice_pos(n_active, slot);
+        if (pos < 0) break;
+        fused_tile<F>(d, b, d.list[pos]);
+    }
+}
+
+// Member descriptors of a batch are read through the constant address space,
+// so their (wavefront-uniform) fields come in with scalar loads, as a single
+// domain's do from the kernel arguments.
+typedef const __attribute__((address_space(4))) DomainDev ConstDomainDev;
+
+// Every member of a batch in one launch: the list holds global tile numbers
+// (member base + tile), and each member keeps its own buffer parity.
+template <typename F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_batch(BatchDev bd, int flip)
+{
+    ConstDomainDev *doms = (ConstDomainDev *)bd.doms;
+    const int n_active = bd.count[flip];
+    for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
+        const int pos = slice_pos(n_active, slot);
+        if (pos < 0) break;
+        const int G = bd.list[pos];
+        const int m = bd.tdom[G];
+        fused_tile<F>(*(const DomainDev *)&doms[m], bd.par[m] ^ flip, G - bd.base[m]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Active tiles of the coming step.  A tile is tested with its 9 flag bytes
 // loaded together.
@@ -433,13 +481,11 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
 // step parity b (the list keeps each block's tiles together and in order).
 // The counter of the other parity, read by nobody during this step, is reset
 // for the next one, so no memset is needed between steps.
-__global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)
+__device__ __forceinline__ void append_active(int a, int id, int *count_b, int *count_other, int *list)
 {
     __shared__ int wsum[4];
     __shared__ int base;
     const int tid = (int)threadIdx.x;
-    const int g = (int)blockIdx.x * 256 + tid;
-    const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
     const int lane = tid & 63, w = tid >> 6;
     int incl = a;
     for (int o = 1; o < 64; o <<= 1) {
@@ -454,10 +500,29 @@ __global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_acti
         before += (k < w) ? s : 0;
         total += s;
     }
-    if (tid == 0) base = total ? atomicAdd(&d.count[b], total) : 0;
-    if (blockIdx.x == 0 && tid == 0) d.count[b ^ 1] = 0;
+    if (tid == 0) base = total ? atomicAdd(count_b, total) : 0;
+    if (blockIdx.x == 0 && tid == 0) *count_other = 0;
     __syncthreads();
-    if (a) d.list[base + before + incl - 1] = g;
+    if (a) list[base + before + incl - 1] = id;
+}
+
+__global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)
+{
+    const int g = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
+    append_active(a, g, &d.count[b], &d.count[b ^ 1], d.list);
+}
+
+// The same over a batch's global tile table: each member's own flags decide.
+__global__ __launch_bounds__(256) void k_active_batch(BatchDev bd, int flip, int all_active)
+{
+    const int G = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    int a = 0;
+    if (G < bd.ntiles) {
+        const int m = bd.tdom[G];
+        a = tile_active(bd.doms[m], G - bd.base[m], all_active);
+    }
+    append_active(a, G, &bd.count[flip], &bd.count[flip ^ 1], bd.list);
 }
 
 }  // namespace
@@ -468,13 +533,32 @@ hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_fused(const DomainDev &d, int b, hipStream_t s)
+hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, hipStream_t s)
 {
-    // One workgroup per tile at most; the 8-way XCD slicing needs a multiple of 8.
-    const int grid = (d.ntiles + 7) / 8 * 8;
-    if (d.bulk32)
-        hipLaunchKernelGGL(k_fused<float>, dim3(grid), dim3(64), 0, s, d, b);
+    hipLaunchKernelGGL(k_active_batch, dim3((bd.ntiles + 255) / 256), dim3(256), 0, s, bd, flip, all_active);
+    return hipGetLastError();
+}
+
+// grid: workgroups (a multiple of 8), at most one per tile; fewer make a
+// persistent grid.
+hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s)
+{
+    const bool loop = grid < (d.ntiles + 7) / 8 * 8;
+    if (d.bulk32) {
+        if (loop) hipLaunchKernelGGL(k_fused_loop<float>, dim3(grid), dim3(64), 0, s, d, b);
+        else hipLaunchKernelGGL(k_fused<float>, dim3(grid), dim3(64), 0, s, d, b);
+    } else {
+        if (loop) hipLaunchKernelGGL(k_fused_loop<double>, dim3(grid), dim3(64), 0, s, d, b);
+        else hipLaunchKernelGGL(k_fused<double>, dim3(grid), dim3(64), 0, s, d, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s)
+{
+    if (bulk32)
+        hipLaunchKernelGGL(k_fused_batch<float>, dim3(grid), dim3(64), 0, s, bd, flip);
     else
-        hipLaunchKernelGGL(k_fused<double>, dim3(grid), dim3(64), 0, s, d, b);
+        hipLaunchKernelGGL(k_fused_batch<double>, dim3(grid), dim3(64), 0, s, bd, flip);
     return hipGetLastError();
 }

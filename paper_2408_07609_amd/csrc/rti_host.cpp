@@ -13,10 +13,9 @@
 #include <string>
 #include <vector>
 
-#include "rti.h"
-#include "rti_internal.h"
+#include "rti_runtime.h"
 
-namespace {
+namespace rti_rt {
 
 thread_local std::string g_err;
 
@@ -31,55 +30,35 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(call)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (call);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(RTI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int kGraphSteps = 20;   // steps per captured graph (even: parity returns)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct LevelPlan {
-    int nx, ny, pitch, parent, off_i, off_j;
-    double dx, ox, oy;
-    size_t eta_bytes;                       // one pitched FP64 cell array (eta)
-    size_t cells_bytes, xf_bytes, yf_bytes; // one pitched array of h/maxima, M, N in the bulk precision
-    int tiles_x, tiles_y, s_tiles_x, s_tiles_y;
-};
-
-struct Plan {
-    std::vector<LevelPlan> lv;
-    std::vector<uint8_t> tinfo;   // static bits per fused-kernel tile (TI_*)
-    std::vector<int32_t> tcells;  // cells of the level inside each tile
-    size_t elem = sizeof(double); // element size of h, maxima, M, N
-    size_t bytes = 0;
-    int ntiles = 0, s_ntiles = 0;
-};
-
 // Static bits of every tile.  A tile's extended region (its cells plus the
 // 2-cell halo its stencil reads, plus one for safety) decides: TI_EDGE when it
 // reaches within 3 cells of the level's outer faces (open sides, injected
 // child edges); TI_CHILD when it reaches within 3 parent cells of a child's
 // footprint boundary (ring cells, edge faces).  Both pin the tile.
-void tile_info(const rti_domain_desc *d, Plan &plan)
+void plan_tiles(Plan &plan, int th)
 {
-    plan.tinfo.assign(plan.ntiles, 0);
-    plan.tcells.assign(plan.ntiles, 0);
+    plan.th = th;
+    int ntiles = 0;
+    for (auto &p : plan.lv) {
+        p.tiles_x = (p.nx + 1 + RTI_TW - 1) / RTI_TW;
+        p.tiles_y = (p.ny + 1 + th - 1) / th;
+        ntiles += p.tiles_x * p.tiles_y;
+    }
+    plan.ntiles = ntiles;
+    plan.tinfo.assign(ntiles, 0);
+    plan.tcells.assign(ntiles, 0);
+    const int nlev = (int)plan.lv.size();
     int base = 0;
-    for (int l = 0; l < d->n_levels; ++l) {
+    for (int l = 0; l < nlev; ++l) {
         const LevelPlan &p = plan.lv[l];
         for (int ty = 0; ty < p.tiles_y; ++ty) {
             for (int tx = 0; tx < p.tiles_x; ++tx) {
                 const int ax = tx * RTI_TW - 3, bx = tx * RTI_TW + RTI_TW + 2;
-                const int ay = ty * RTI_TH - 3, by = ty * RTI_TH + RTI_TH + 2;
+                const int ay = ty * th - 3, by = ty * th + th + 2;
                 uint8_t bits = 0;
                 if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) bits |= TI_EDGE | TI_PINNED;
-                for (int k = l + 1; k < d->n_levels; ++k) {
-                    const rti_level_desc &C = d->levels[k];
+                for (int k = l + 1; k < nlev; ++k) {
+                    const LevelPlan &C = plan.lv[k];
                     if (C.parent != l) continue;
                     const int fx0 = C.off_i, fx1 = C.off_i + C.nx / 3 - 1;   // footprint, inclusive
                     const int fy0 = C.off_j, fy1 = C.off_j + C.ny / 3 - 1;
@@ -88,13 +67,33 @@ void tile_info(const rti_domain_desc *d, Plan &plan)
                     if (meets_outer && !inside_inner) bits |= TI_CHILD | TI_PINNED;
                 }
                 plan.tinfo[base + ty * p.tiles_x + tx] = bits;
-                const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(RTI_TH, p.ny - ty * RTI_TH);
+                const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
                 plan.tcells[base + ty * p.tiles_x + tx] = std::max(0, w) * std::max(0, hgt);
             }
         }
         base += p.tiles_x * p.tiles_y;
     }
 }
+
+int fused_grid(int ntiles, bool persistent, int cu_count)
+{
+    int grid = (ntiles + 7) / 8 * 8;
+    if (persistent) {
+        // 3 wavefronts per SIMD, 4 SIMDs per compute unit (the fused kernel's occupancy)
+        const int resident = std::max(8, cu_count * 12 / 8 * 8);
+        grid = std::min(grid, resident);
+    }
+    return std::max(grid, 8);
+}
+
+}  // namespace rti_rt
+
+using namespace rti_rt;
+
+static_assert(RTI_TH == RTI_TILE_ROWS_DEFAULT && RTI_TH_MIN == RTI_TILE_ROWS_MIN && RTI_TH_MAX == RTI_TILE_ROWS_MAX,
+              "tile heights of the ABI and the kernels disagree");
+
+namespace {
 
 // Validate the descriptor and lay the domain out in device memory.
 int plan_domain(const rti_domain_desc *d, Plan &plan)
@@ -113,7 +112,7 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     if (d->precision == RTI_FP32_BULK && (d->flags & RTI_FLAG_PHASED))
         return fail(RTI_EINVAL, "the per-phase kernels are FP64 only");
     plan.elem = (d->precision == RTI_FP32_BULK) ? sizeof(float) : sizeof(double);
-    if (d->flags & ~(RTI_FLAG_NO_GRAPH | RTI_FLAG_NO_ACTIVE | RTI_FLAG_PHASED))
+    if (d->flags & ~(RTI_FLAG_NO_GRAPH | RTI_FLAG_NO_ACTIVE | RTI_FLAG_PHASED | RTI_FLAG_PERSISTENT))
         return fail(RTI_EINVAL, "unknown flags 0x%x", d->flags);
 
     plan.lv.assign(d->n_levels, LevelPlan{});
@@ -174,46 +173,27 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     }
     // Tiles and bytes.
     size_t bytes = 0;
-    int ntiles = 0, s_ntiles = 0;
+    int s_ntiles = 0;
     for (auto &p : plan.lv) {
-        p.tiles_x = (p.nx + 1 + RTI_TW - 1) / RTI_TW;
-        p.tiles_y = (p.ny + 1 + RTI_TH - 1) / RTI_TH;
         p.s_tiles_x = (p.nx + 63) / 64;
         p.s_tiles_y = (p.ny + 3) / 4;
-        ntiles += p.tiles_x * p.tiles_y;
         s_ntiles += p.s_tiles_x * p.s_tiles_y;
         // eta x2 (FP64); h, zmax, M x2, N x2 (bulk precision)
         bytes += 2 * p.eta_bytes + 2 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
     }
+    plan.level_bytes = bytes;
+    plan_tiles(plan, RTI_TH_MIN);             // the most tiles any height gives
+    const int cap = plan.ntiles;
     // tile info, tile flags, active list, control block (count, divergence flag)
-    bytes += 2 * align_up((size_t)ntiles, kAlign) + align_up((size_t)ntiles * 4, kAlign) + kAlign;
+    bytes += 2 * align_up((size_t)cap, kAlign) + align_up((size_t)cap * 4, kAlign) + kAlign;
     plan.bytes = bytes;
-    plan.ntiles = ntiles;
+    plan.ntiles_cap = cap;
     plan.s_ntiles = s_ntiles;
-    tile_info(d, plan);
+    plan_tiles(plan, RTI_TH);
     return RTI_OK;
 }
 
 }  // namespace
-
-struct rti_domain {
-    Plan plan;
-    DomainDev dev{};
-    hipStream_t stream = nullptr;        // borrowed
-    hipStream_t capture = nullptr;       // private, for graph capture
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    void *mem = nullptr;                 // base of the carved memory
-    bool owns_mem = false;
-    int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag
-    uint8_t *tinfo = nullptr;
-    int cur = 0;                         // buffer holding the current state
-    int64_t steps = 0;
-    uint32_t flags = 0;
-    double dt = 0.0;
-    bool diverged = false;
-    int device = 0;
-};
 
 namespace {
 
@@ -236,7 +216,7 @@ int carve(rti_domain *D)
         L.N[0] = based(pl.yf_bytes, D->plan.elem);
         L.N[1] = based(pl.yf_bytes, D->plan.elem);
     }
-    const size_t nt = (size_t)D->plan.ntiles;
+    const size_t nt = (size_t)D->plan.ntiles_cap;
     D->tinfo = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.tinfo = D->tinfo;
     D->dev.tflag = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
@@ -292,13 +272,23 @@ int check_level(const rti_domain *D, int level)
     return RTI_OK;
 }
 
+}  // namespace
+
 // Any host-side change of the state forgets the quiescence history, so the
 // next two steps compute every tile.
-int forget_quiet(rti_domain *D)
+int rti_rt::forget_quiet(rti_domain *D)
 {
     HIP_TRY(hipMemsetAsync(D->dev.tflag, 0, (size_t)D->plan.ntiles, D->stream));
     return RTI_OK;
 }
+
+int rti_rt::reset_counts(rti_domain *D)
+{
+    HIP_TRY(hipMemsetAsync(D->ctrl, 0, 2 * sizeof(int), D->stream));
+    return RTI_OK;
+}
+
+namespace {
 
 // Initial water level of a level (host, packed) -> both eta buffers; zero
 // fluxes; maxima at the initial values.  eta is clipped to the ground.
@@ -336,7 +326,7 @@ int launch_step(rti_domain *D, int b, hipStream_t s)
         HIP_TRY(launch_jnq(D->dev, b, s));
     } else {
         HIP_TRY(launch_active(D->dev, b, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
-        HIP_TRY(launch_fused(D->dev, b, s));
+        HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s));
     }
     return RTI_OK;
 }
@@ -355,9 +345,10 @@ int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
     // the last step read buffer cur^1, so its list was counted in ctrl[cur^1]
     HIP_TRY(hipMemcpyAsync(&n, D->ctrl + (D->cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, D->stream));
     HIP_TRY(hipStreamSynchronize(D->stream));
-    if (D->steps == 0) n = D->dev.ntiles;
+    const bool fresh = D->steps == D->tiles_step;   // no step since the tile tables were built
+    if (fresh) n = D->dev.ntiles;
     std::vector<int32_t> list(n);
-    if (D->steps > 0 && n > 0) {
+    if (!fresh && n > 0) {
         HIP_TRY(hipMemcpyAsync(list.data(), D->dev.list, sizeof(int32_t) * n, hipMemcpyDeviceToHost, D->stream));
         HIP_TRY(hipStreamSynchronize(D->stream));
     } else {
@@ -367,6 +358,43 @@ int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
     for (int g : list) c += D->plan.tcells[g];
     *tiles = n;
     *cells = c;
+    return RTI_OK;
+}
+
+void drop_graphs(rti_domain *D)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (D->exec[p]) (void)hipGraphExecDestroy(D->exec[p]);
+        if (D->graph[p]) (void)hipGraphDestroy(D->graph[p]);
+        D->exec[p] = nullptr;
+        D->graph[p] = nullptr;
+    }
+}
+
+// Rebuild the fused kernel's tile tables for tile height th (synchronises).
+int retile(rti_domain *D, int th)
+{
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    plan_tiles(D->plan, th);
+    DomainDev &dv = D->dev;
+    dv.th = th;
+    dv.ntiles = D->plan.ntiles;
+    int base = 0;
+    for (int k = 0; k < dv.nlev; ++k) {
+        const LevelPlan &p = D->plan.lv[k];
+        dv.lv[k].tiles_x = p.tiles_x;
+        dv.lv[k].tiles_y = p.tiles_y;
+        dv.lv[k].tile_base = base;
+        base += p.tiles_x * p.tiles_y;
+    }
+    HIP_TRY(hipMemcpyAsync(D->tinfo, D->plan.tinfo.data(), D->plan.tinfo.size(), hipMemcpyHostToDevice, D->stream));
+    int rc = forget_quiet(D);
+    if (!rc) rc = reset_counts(D);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    drop_graphs(D);
+    D->tiles_step = D->steps;
+    D->gen += 1;
     return RTI_OK;
 }
 
@@ -399,7 +427,7 @@ int build_graph(rti_domain *D, int parity)
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char *rti_last_error(void) { return g_err.c_str(); }
+const char *rti_last_error(void) { return rti_rt::g_err.c_str(); }
 
 const char *rti_strerror(int code)
 {
@@ -452,9 +480,10 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         D->flags = desc->flags;
         D->dt = desc->dt;
         hipError_t e = hipGetDevice(&D->device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&D->cu_count, hipDeviceAttributeMultiprocessorCount, D->device);
         if (e != hipSuccess) {
             delete D;
-            return fail(RTI_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+            return fail(RTI_EHIP, "querying the device failed: %s", hipGetErrorString(e));
         }
         if (arena) {
             D->mem = arena;
@@ -468,6 +497,7 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         }
         DomainDev &dv = D->dev;
         dv.nlev = desc->n_levels;
+        dv.th = plan.th;
         dv.ntiles = plan.ntiles;
         dv.s_ntiles = plan.s_ntiles;
         for (int s = 0; s < 4; ++s) dv.bc[s] = desc->bc[s];
@@ -611,6 +641,7 @@ int rti_step(rti_domain *D, int64_t nsteps)
     try {
         if (!D) return fail(RTI_EINVAL, "domain is NULL");
         if (nsteps < 0) return fail(RTI_EINVAL, "nsteps %lld < 0", (long long)nsteps);
+        if (D->batch) return fail(RTI_ESTATE, "the domain is in a batch; step the batch");
         if (D->diverged) return fail(RTI_EDIVERGED, "the domain diverged earlier");
         const bool graphs = !(D->flags & RTI_FLAG_NO_GRAPH);
         while (nsteps > 0) {
@@ -647,6 +678,7 @@ int rti_run(rti_domain *D, double t_end)
 {
     if (!D) return fail(RTI_EINVAL, "domain is NULL");
     if (!std::isfinite(t_end) || t_end < 0.0) return fail(RTI_EINVAL, "t_end %g", t_end);
+    if (D->batch) return fail(RTI_ESTATE, "the domain is in a batch; step the batch");
     const int64_t target = (int64_t)std::llround(t_end / D->dt);
     if (target > D->steps) {
         int rc = rti_step(D, target - D->steps);
@@ -729,6 +761,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
                 double *avg_cells)
 {
     if (!D || !ms || !n_kinds || cap < 1 || nsteps < 1) return fail(RTI_EINVAL, "bad argument");
+    if (D->batch) return fail(RTI_ESTATE, "the domain is in a batch; profile the batch");
     static const char *kNames[K_NKINDS] = {"k_mass", "k_jnz", "k_momentum", "k_jnq", "k_fused", "k_active", "k_finite"};
     double sum[K_NKINDS] = {0};
     int cnt[K_NKINDS] = {0};
@@ -756,7 +789,9 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
         } else {
             if (e == hipSuccess) e = launch_active(D->dev, b, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, D->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
-            if (e == hipSuccess) e = launch_fused(D->dev, b, D->stream);
+            if (e == hipSuccess)
+                e = launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count),
+                                 D->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
             kinds[0] = K_ACTIVE; kinds[1] = K_FUSED;
             nk = 2;
@@ -804,14 +839,121 @@ int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total, int64_t *ce
     return RTI_OK;
 }
 
+int rti_domain_set_tile_rows(rti_domain *D, int32_t rows)
+{
+    try {
+        if (!D) return fail(RTI_EINVAL, "domain is NULL");
+        if (rows < RTI_TILE_ROWS_MIN || rows > RTI_TILE_ROWS_MAX)
+            return fail(RTI_EINVAL, "tile rows %d outside [%d, %d]", rows, RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX);
+        if (rows == D->plan.th) return RTI_OK;
+        return retile(D, rows);
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+int rti_domain_tile_rows(const rti_domain *D, int32_t *rows)
+{
+    if (!D || !rows) return fail(RTI_EINVAL, "NULL argument");
+    *rows = D->plan.th;
+    return RTI_OK;
+}
+
+int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double *ms_out)
+{
+    if (!D) return fail(RTI_EINVAL, "domain is NULL");
+    if (nsteps < 1) return fail(RTI_EINVAL, "nsteps %d < 1", nsteps);
+    if (D->batch) return fail(RTI_ESTATE, "the domain is in a batch");
+    if (D->flags & RTI_FLAG_PHASED) return fail(RTI_EINVAL, "the per-phase kernels have no tiles to tune");
+    if (D->diverged) return fail(RTI_EDIVERGED, "the domain diverged earlier");
+    static const int kCand[] = {4, 5, 6, 8, 10, 12, 16, 24};
+    void *snap = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const int cur0 = D->cur;
+    const int64_t steps0 = D->steps;
+    int best = D->plan.th;
+    double best_ms = 0.0;
+    int rc = RTI_OK;
+    auto restore = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice, D->stream));
+        D->cur = cur0;
+        D->steps = steps0;
+        int rc2 = forget_quiet(D);
+        return rc2 ? rc2 : reset_counts(D);
+    };
+    try {
+        HIP_TRY(hipStreamSynchronize(D->stream));
+        hipError_t e = hipMalloc(&snap, D->plan.level_bytes);
+        if (e != hipSuccess) return fail(RTI_ENOMEM, "autotune snapshot of %zu bytes: %s", D->plan.level_bytes, hipGetErrorString(e));
+        e = hipMemcpyAsync(snap, D->mem, D->plan.level_bytes, hipMemcpyDeviceToDevice, D->stream);
+        if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+        if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+        if (e != hipSuccess) rc = fail(RTI_EHIP, "autotune set-up: %s", hipGetErrorString(e));
+        bool first = true;
+        for (int c : kCand) {
+            if (rc) break;
+            if ((rc = retile(D, c)) || (rc = restore())) break;
+            for (int k = 0; k < 2 && !rc; ++k) {      // untimed: the skip history settles
+                rc = launch_step(D, D->cur, D->stream);
+                D->cur ^= 1;
+                D->steps += 1;
+            }
+            if (rc) break;
+            e = hipEventRecord(ev[0], D->stream);
+            for (int k = 0; k < nsteps && !rc && e == hipSuccess; ++k) {
+                rc = launch_step(D, D->cur, D->stream);
+                D->cur ^= 1;
+                D->steps += 1;
+            }
+            if (!rc && e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
+            if (!rc && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float t = 0.0f;
+            if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (!rc && e != hipSuccess) rc = fail(RTI_EHIP, "autotune timing: %s", hipGetErrorString(e));
+            if (rc) break;
+            const double ms = (double)t / nsteps;
+            if (first || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+                first = false;
+            }
+        }
+        if (!rc) rc = retile(D, best);
+        if (!rc) rc = restore();
+        if (!rc) {
+            e = hipStreamSynchronize(D->stream);
+            if (e != hipSuccess) rc = fail(RTI_EHIP, "autotune restore: %s", hipGetErrorString(e));
+        }
+    } catch (...) {
+        rc = fail(RTI_EINVAL, "unexpected exception");
+    }
+    if (rc && snap) {
+        // leave the domain as it was, whatever failed
+        (void)hipStreamSynchronize(D->stream);
+        (void)hipMemcpy(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice);
+        D->cur = cur0;
+        D->steps = steps0;
+        (void)forget_quiet(D);
+        (void)reset_counts(D);
+        (void)hipStreamSynchronize(D->stream);
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (snap) (void)hipFree(snap);
+    if (rc) return rc;
+    if (rows_out) *rows_out = best;
+    if (ms_out) *ms_out = best_ms;
+    return RTI_OK;
+}
+
 void rti_domain_destroy(rti_domain *D)
 {
     if (!D) return;
+    if (D->batch) batch_forget_member(D->batch, D);
     (void)hipStreamSynchronize(D->stream);
-    for (int p = 0; p < 2; ++p) {
-        if (D->exec[p]) (void)hipGraphExecDestroy(D->exec[p]);
-        if (D->graph[p]) (void)hipGraphDestroy(D->graph[p]);
-    }
+    drop_graphs(D);
     if (D->capture) (void)hipStreamDestroy(D->capture);
     if (D->owns_mem && D->mem) (void)hipFree(D->mem);
     delete D;

@@ -10,13 +10,18 @@
 
 // Tile of the fused kernel: one wavefront of 64 lanes covers 64 columns and
 // writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
-// right); it streams up RTI_TH output rows (plus 3 rows of pipeline warm-up).
-// Short tiles give many wavefronts (the launch drains evenly and many loads
-// are in flight); 6 rows measured best on gfx950 with RTI_PD = 2.
+// right); it streams up DomainDev::th output rows (plus 3 rows of pipeline
+// warm-up).  Short tiles give many wavefronts (the launch drains evenly and
+// many loads are in flight); RTI_TH rows, the default, measured best on
+// gfx950 with RTI_PD = 2.  The height is a per-domain setting between
+// RTI_TH_MIN (the 3x3 tile neighbourhood of the skip rule must cover the
+// stencil's reach) and RTI_TH_MAX.
 #define RTI_TW 60
 #ifndef RTI_TH
 #define RTI_TH 6
 #endif
+#define RTI_TH_MIN 4
+#define RTI_TH_MAX 64
 // Rows of loads the fused kernel keeps in flight ahead of the row it computes,
 // and the rows of its rolling window (rows t-2 .. t+RTI_PD).  2 still fits
 // 3 wavefronts per SIMD (<= 168 VGPRs); deeper prefetch drops to 2.
@@ -58,6 +63,7 @@ struct LevelDev {
 
 struct DomainDev {
     int32_t nlev;
+    int32_t th;                            // output rows of a fused-kernel tile
     int32_t ntiles;                        // fused-kernel tiles over all levels
     int32_t s_ntiles;                      // per-phase-kernel tiles over all levels
     int32_t bc[4];
@@ -69,6 +75,19 @@ struct DomainDev {
     int32_t *list;                         // ntiles: active tiles of the current step
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
     LevelDev lv[RTI_MAX_LEVELS_DEV];
+};
+
+// A batch of domains stepped together: member m's tiles are global tiles
+// base[m] .. base[m+1]-1 of one table, and its state buffer at step parity
+// flip is par[m] ^ flip.
+struct BatchDev {
+    const DomainDev *doms;                 // n members (device copy of each DomainDev)
+    const int32_t *base;                   // n + 1 entries
+    const uint16_t *tdom;                  // ntiles: member of each global tile
+    const uint8_t *par;                    // n
+    int32_t n, ntiles;
+    int32_t *list;                         // ntiles: active global tiles of the current step
+    int32_t *count;                        // [flip]
 };
 
 // Kernel kinds (for profiling).
@@ -84,4 +103,6 @@ hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s);
-hipError_t launch_fused(const DomainDev &d, int b, hipStream_t s);
+hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
+hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, hipStream_t s);
+hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s);

@@ -1,0 +1,94 @@
+// rti_runtime.h -- host-side internals shared by the domain runtime
+// (rti_host.cpp) and the batch runtime (rti_batch.cpp).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "rti.h"
+#include "rti_internal.h"
+
+namespace rti_rt {
+
+// Records the message of the calling thread's last failure; returns code.
+int fail(int code, const char *fmt, ...);
+
+#define HIP_TRY(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::rti_rt::fail(RTI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kGraphSteps = 20;   // steps per captured graph (even: parity returns)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct LevelPlan {
+    int nx, ny, pitch, parent, off_i, off_j;
+    double dx, ox, oy;
+    size_t eta_bytes;                       // one pitched FP64 cell array (eta)
+    size_t cells_bytes, xf_bytes, yf_bytes; // one pitched array of h/maxima, M, N in the bulk precision
+    int tiles_x, tiles_y, s_tiles_x, s_tiles_y;
+};
+
+struct Plan {
+    std::vector<LevelPlan> lv;
+    std::vector<uint8_t> tinfo;   // static bits per fused-kernel tile (TI_*)
+    std::vector<int32_t> tcells;  // cells of the level inside each tile
+    size_t elem = sizeof(double); // element size of h, maxima, M, N
+    size_t level_bytes = 0;       // the level arrays (state, bathymetry, maxima), first in memory
+    size_t bytes = 0;
+    int ntiles = 0, s_ntiles = 0;
+    int ntiles_cap = 0;           // tile tables are sized for the smallest tile height
+    int th = RTI_TH;              // tile rows of the fused kernel
+};
+
+// Tile grid, static tile bits and per-tile cell counts of tile height th.
+void plan_tiles(Plan &plan, int th);
+
+// Workgroups of a fused launch over ntiles tiles: one per tile, or a fixed
+// persistent grid of resident wavefronts when that is smaller.
+int fused_grid(int ntiles, bool persistent, int cu_count);
+
+}  // namespace rti_rt
+
+struct rti_batch;
+
+struct rti_domain {
+    rti_rt::Plan plan;
+    DomainDev dev{};
+    hipStream_t stream = nullptr;        // borrowed
+    hipStream_t capture = nullptr;       // private, for graph capture
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    void *mem = nullptr;                 // base of the carved memory
+    bool owns_mem = false;
+    int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag
+    uint8_t *tinfo = nullptr;
+    int cur = 0;                         // buffer holding the current state
+    int64_t steps = 0;
+    uint32_t flags = 0;
+    double dt = 0.0;
+    bool diverged = false;
+    int device = 0;
+    int cu_count = 256;
+    uint64_t gen = 0;                    // bumped whenever dev or the tile tables change
+    int64_t tiles_step = 0;              // step count when the tile tables were last rebuilt
+    rti_batch *batch = nullptr;          // the batch this domain belongs to
+};
+
+namespace rti_rt {
+// Used by the batch runtime.
+int forget_quiet(rti_domain *D);
+// Zero both active-tile counters.  A step's list is appended at its parity's
+// counter, which the step before resets; whenever a domain's parity moves
+// without its own steps (batch steps, autotune restore) the counters are
+// zeroed so no stale count survives.
+int reset_counts(rti_domain *D);
+void batch_forget_member(rti_batch *B, rti_domain *D);   // a member is being destroyed
+}  // namespace rti_rt

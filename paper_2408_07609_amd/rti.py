@@ -21,8 +21,9 @@ RTI_OK, RTI_EINVAL, RTI_ENOMEM, RTI_EHIP, RTI_ECFL, RTI_ENEST, RTI_ESTATE, RTI_E
 RTI_FP64, RTI_FP32_BULK = 0, 1
 RTI_BC_OPEN, RTI_BC_WALL = 0, 1
 RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
-RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED = 0x1, 0x2, 0x4
+RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED, RTI_FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 RTI_MAX_LEVELS = 16
+RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX, RTI_TILE_ROWS_DEFAULT = 4, 64, 6
 
 _dptr = ctypes.POINTER(ctypes.c_double)
 
@@ -69,7 +70,19 @@ FUNCTIONS = {
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
     "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]),
+    "rti_domain_set_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rti_domain_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "rti_domain_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
     "rti_domain_destroy": (None, [ctypes.c_void_p]),
+    "rti_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "rti_batch_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rti_batch_remove": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rti_batch_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "rti_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "rti_batch_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "rti_batch_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dptr, _dptr, _dptr]),
+    "rti_batch_destroy": (None, [ctypes.c_void_p]),
     "rti_last_error": (ctypes.c_char_p, []),
     "rti_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -179,8 +192,65 @@ def rti_active_tiles(dom: int):
     return int(a.value), int(t.value), int(c.value)
 
 
+def rti_domain_set_tile_rows(dom: int, rows: int):
+    _check(LIB.rti_domain_set_tile_rows(dom, int(rows)))
+
+
+def rti_domain_tile_rows(dom: int) -> int:
+    n = ctypes.c_int32(0)
+    _check(LIB.rti_domain_tile_rows(dom, ctypes.byref(n)))
+    return int(n.value)
+
+
+def rti_domain_autotune(dom: int, nsteps: int):
+    """Returns (tile rows chosen, ms per step at that height)."""
+    rows, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(LIB.rti_domain_autotune(dom, int(nsteps), ctypes.byref(rows), ctypes.byref(ms)))
+    return int(rows.value), float(ms.value)
+
+
 def rti_domain_destroy(dom: int | None):
     LIB.rti_domain_destroy(dom)
+
+
+def rti_batch_create(members, stream_ptr: int | None, flags: int = 0) -> int:
+    arr = (ctypes.c_void_p * max(1, len(members)))(*members)
+    out = ctypes.c_void_p(0)
+    _check(LIB.rti_batch_create(arr, len(members), stream_ptr, int(flags), ctypes.byref(out)))
+    return out.value
+
+
+def rti_batch_add(batch: int, dom: int):
+    _check(LIB.rti_batch_add(batch, dom))
+
+
+def rti_batch_remove(batch: int, dom: int):
+    _check(LIB.rti_batch_remove(batch, dom))
+
+
+def rti_batch_size(batch: int) -> int:
+    n = ctypes.c_int32(0)
+    _check(LIB.rti_batch_size(batch, ctypes.byref(n)))
+    return int(n.value)
+
+
+def rti_batch_step(batch: int, nsteps: int):
+    _check(LIB.rti_batch_step(batch, int(nsteps)))
+
+
+def rti_batch_sync(batch: int):
+    _check(LIB.rti_batch_sync(batch))
+
+
+def rti_batch_profile(batch: int, nsteps: int):
+    """Returns (fused ms per launch, active-list ms per launch, cells computed per step)."""
+    f, a, c = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(LIB.rti_batch_profile(batch, int(nsteps), ctypes.byref(f), ctypes.byref(a), ctypes.byref(c)))
+    return float(f.value), float(a.value), float(c.value)
+
+
+def rti_batch_destroy(batch: int | None):
+    LIB.rti_batch_destroy(batch)
 
 
 def rti_last_error() -> str:
@@ -300,3 +370,69 @@ class Domain:
 
     def active_tiles(self):
         return rti_active_tiles(self._h)
+
+    # -- tile shape
+    @property
+    def tile_rows(self):
+        return rti_domain_tile_rows(self._h)
+
+    def set_tile_rows(self, rows):
+        rti_domain_set_tile_rows(self._h, rows)
+
+    def autotune(self, nsteps=20):
+        """Time every candidate tile height from the current state, keep the
+        fastest, restore the state.  Returns (rows, ms per step)."""
+        return rti_domain_autotune(self._h, nsteps)
+
+
+class Batch:
+    """Domains stepped together by one launch per step over all their tiles.
+    Members must have been created on the stream given here (default: torch's
+    current stream) with one precision."""
+
+    def __init__(self, members=(), flags=0, device="cuda:0", stream=None):
+        import torch
+        dev = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.members = list(members)
+        with torch.cuda.device(dev):
+            self._h = rti_batch_create([m._h for m in self.members], self.stream.cuda_stream, flags)
+
+    def add(self, dom):
+        rti_batch_add(self._h, dom._h)
+        self.members.append(dom)
+
+    def remove(self, dom):
+        rti_batch_remove(self._h, dom._h)
+        self.members.remove(dom)
+
+    def __len__(self):
+        return rti_batch_size(self._h)
+
+    def step(self, n=1):
+        rti_batch_step(self._h, n)
+
+    def sync(self):
+        rti_batch_sync(self._h)
+
+    def profile(self, nsteps):
+        """(fused ms per launch, active-list ms per launch, cells computed per step)."""
+        return rti_batch_profile(self._h, nsteps)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            rti_batch_destroy(self._h)
+            self._h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

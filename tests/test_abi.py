@@ -111,3 +111,23 @@ def test_footprint_matches_layout():
     if big is not None:
         d2, k2 = rti.make_desc(big.levels, big.dx0, big.dt)
         assert rti.rti_domain_footprint(d2) < 288e9 / 50
+
+
+def test_tile_and_batch_calls_validate_before_the_gpu():
+    with pytest.raises(rti.RtiError) as ei:
+        rti.rti_domain_set_tile_rows(None, 6)
+    assert ei.value.code == rti.RTI_EINVAL
+    with pytest.raises(rti.RtiError) as ei:
+        rti.rti_domain_autotune(None, 5)
+    assert ei.value.code == rti.RTI_EINVAL
+    with pytest.raises(rti.RtiError) as ei:
+        rti.rti_batch_create([], None, 0x100)          # unknown batch flag
+    assert ei.value.code == rti.RTI_EINVAL
+    with pytest.raises(rti.RtiError) as ei:
+        rti.rti_batch_step(None, 1)
+    assert ei.value.code == rti.RTI_EINVAL
+    with pytest.raises(rti.RtiError) as ei:
+        rti.rti_batch_size(None)
+    assert ei.value.code == rti.RTI_EINVAL
+    rti.rti_batch_destroy(None)                          # NULL is a no-op
+    assert rti.RTI_TILE_ROWS_MIN <= rti.RTI_TILE_ROWS_DEFAULT <= rti.RTI_TILE_ROWS_MAX
