@@ -7,12 +7,16 @@ Default workload: the 4-level nest at 810/270/90/30 m (1200x1000, 900^2,
 1500^2, 2400^2 = 10.02 M cells) over a seeded synthetic coast, dt = 0.2 s,
 3 m elliptic uplift, run for the whole 3600 s (18,000 steps) from t = 0,
 inputs resident in HBM.  Prints one JSON line on stdout; progress on stderr.
+--config c4: the batched ensemble (48 uneven scenarios, FP32-bulk, one batch);
+--config c5: forecast serving (Poisson arrivals, continuous batching, p50/p99
+time to forecast).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -96,23 +100,233 @@ def cpu_baseline(sc, seconds):
                 sample=f"{sc.name}: all {sc.cells} cells, steps 1..{done} from t=0 ({el:.1f} s of CPU work)")
 
 
+def make_domain(sc, precision, flags=0):
+    from paper_2408_07609_amd import Domain
+    d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
+               x0=sc.x0, y0=sc.y0, flags=flags, device="cuda:0", precision=precision)
+    d.set_source(*sc.source.astuple())
+    return d
+
+
+def bench_batch(args):
+    """The batched ensemble (C4): 48 uneven scenarios stepped as one batch
+    (one active-list launch and one fused launch per step over all members'
+    tiles, HIP graphs), tile heights autotuned per member."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    import scenarios
+    from paper_2408_07609_amd import RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64, Batch
+
+    prec = RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64
+    scs = scenarios.c4()
+    cells = sum(sc.cells for sc in scs)
+    steps = args.steps if args.steps is not None else 2000
+    log(f"c4: {len(scs)} members, {cells} cells, {steps} timed steps, {args.precision}")
+
+    def build(precision, tune):
+        ds = [make_domain(sc, precision) for sc in scs]
+        rows = []
+        if tune:
+            for d in ds:
+                rows.append(d.autotune(8)[0])
+        return ds, rows
+
+    ds, rows = build(prec, True)
+    log(f"autotuned tile rows: {dict(collections.Counter(rows))}")
+    batch = Batch(ds, flags=RTI_FLAG_PERSISTENT if args.persistent else 0)
+    batch.step(args.warmup)
+    batch.sync()
+    stream = batch.stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"timed {steps} batch steps: {wall:.3f} s")
+    fused_ms, active_ms, prof_cells = batch.profile(args.profile_steps)
+    bpc = BYTES_PER_CELL_FP32_BULK["k_fused"] if prec == RTI_FP32_BULK else BYTES_PER_CELL["k_fused"]
+    achieved = bpc * prof_cells / (fused_ms * 1e-3) / 1e9
+    finest = [d.get_state(len(d.levels) - 1)[0] for d in ds]
+    assert all(np.all(np.isfinite(e)) for e in finest), "non-finite state after the timed run"
+    done = ds[0].steps
+    batch.close()
+
+    # the same members one after another (each replays its own graphs)
+    seq_steps = max(20, min(steps, 400) // 20 * 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in ds:
+        d.step(seq_steps)
+    torch.cuda.synchronize()
+    seq = cells * seq_steps / (time.perf_counter() - t0)
+    log(f"members one after another: {seq:.4g} cell-updates/s ({seq_steps} steps each)")
+
+    out = {
+        "metric": "cell-updates/s",
+        "value": cells * steps / wall,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == RTI_FP64 else "f32-bulk (f64 water level)",
+        "data": "synthetic",
+        "config": {
+            "workload": "c4-ensemble48",
+            "members": len(scs),
+            "cells": cells,
+            "member_cells": [sc.cells for sc in scs],
+            "tile_rows": rows,
+            "persistent": bool(args.persistent),
+            "timed_steps_from": args.warmup,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_fused_batch", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_cell": bpc, "cells_per_launch": prof_cells,
+            "launch_ms": fused_ms, "kernel_ms": {"k_fused_batch": fused_ms, "k_active_batch": active_ms},
+        },
+        "one_after_another": {"value": seq, "unit": "cell-updates/s", "steps_each": seq_steps},
+    }
+    for d in ds:
+        d.close()
+    del ds, finest
+
+    if prec == RTI_FP32_BULK and not args.no_fp64:
+        # The same ensemble in FP64: the FP32-bulk error after compare_steps
+        # steps from t = 0 (max and RMS |d eta| over all cells, max |d maxima|),
+        # then the FP64 rate over the same number of timed steps.
+        log(f"fp64 comparison: {args.compare_steps} steps of both precisions")
+        d32, _ = build(RTI_FP32_BULK, False)
+        d64, _ = build(RTI_FP64, False)
+        for group in (d32, d64):
+            with Batch(group) as b:
+                b.step(args.compare_steps)
+                b.sync()
+        emax = zerr = 0.0
+        esq = 0.0
+        ncell = 0
+        for a32, a64 in zip(d32, d64):
+            for k in range(len(a32.levels)):
+                e32, e64 = a32.get_state(k)[0], a64.get_state(k)[0]
+                de = np.abs(e32 - e64)
+                emax = max(emax, float(de.max()))
+                esq += float(np.sum(de * de))
+                ncell += de.size
+                zerr = max(zerr, float(np.abs(a32.max_inundation(k) - a64.max_inundation(k)).max()))
+            a32.close()
+        b64 = Batch(d64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b64.step(steps)
+        torch.cuda.synchronize()
+        v64 = cells * steps / (time.perf_counter() - t0)
+        b64.close()
+        for d in d64:
+            d.close()
+        out["fp64"] = {"value": v64, "unit": "cell-updates/s", "steps": steps}
+        out["fp32_bulk_error_vs_fp64"] = {"after_steps": args.compare_steps, "eta_max_m": emax,
+                                          "eta_rms_m": math.sqrt(esq / max(1, ncell)), "maxima_max_m": zerr}
+        log(f"fp64 {v64:.4g} cell-updates/s; fp32-bulk error {out['fp32_bulk_error_vs_fp64']}")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        small = min(scs, key=lambda sc: sc.cells if len(sc.levels) == 3 else 1 << 60)
+        out["cpu_baseline"] = cpu_baseline(small, args.cpu_seconds)
+        out["cpu_baseline"]["sample"] += " (the smallest nested member of c4)"
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Forecast serving (C5): Poisson arrivals of requests on six nested
+    sites of 1 M to 47 M cells, admitted by device footprint into one running
+    batch (continuous batching), the clock and the 1-6 h durations compressed
+    by --time-scale.  Runs the same request stream in FP32-bulk and in FP64
+    (unless --precision picks one)."""
+    import torch
+
+    import scenarios
+    from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64
+    from paper_2408_07609_amd.serve import ForecastServer, Request, percentiles
+
+    sites = scenarios.c5_sites()
+    stream = scenarios.c5_requests(sites, count=args.requests, time_scale=args.time_scale)
+    reqs = [Request(i, sites[k], src, steps, t) for i, (k, src, steps, t) in enumerate(stream)]
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.8, args.hbm_gib * 2**30)) if args.hbm_gib else int(free * 0.8)
+    log(f"c5: {len(reqs)} requests over {reqs[-1].arrival:.1f} s, sites {[sc.cells for sc in sites]}, "
+        f"budget {budget / 2**30:.1f} GiB")
+    runs = {}
+    precs = {"fp32-bulk": RTI_FP32_BULK, "fp64": RTI_FP64}
+    order = [args.precision] if "--precision" in sys.argv else ["fp32-bulk", "fp64"]
+    for name in order:
+        srv = ForecastServer(budget, precs[name], chunk_steps=args.chunk)
+        res = srv.run(reqs, log=log if args.verbose else None)
+        srv.close()
+        q = percentiles(res)
+        runs[name] = {"p50_time_to_forecast_s": q["p50"], "p99_time_to_forecast_s": q["p99"],
+                      "cell_updates_per_s": srv.cell_updates / srv.makespan, "makespan_s": srv.makespan,
+                      "cell_updates": srv.cell_updates, "peak_concurrent": srv.peak_members,
+                      "peak_gib": srv.peak_bytes / 2**30}
+        log(f"{name}: {runs[name]}")
+    first = runs[order[0]]
+    out = {
+        "metric": "cell-updates/s",
+        "value": first["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": int(sum(r.steps for r in reqs)),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-bulk (f64 water level)" if order[0] == "fp32-bulk" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "c5-serving", "requests": len(reqs), "sites_cells": [sc.cells for sc in sites],
+                   "arrival_rate_per_min": 2.0, "time_scale": args.time_scale, "chunk_steps": args.chunk,
+                   "hbm_budget_gib": budget / 2**30},
+        "serving": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole configuration)")
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    ap.add_argument("--persistent", action="store_true", help="c4: persistent grid for the batched kernel")
+    ap.add_argument("--no-fp64", action="store_true", help="c4: skip the FP64 comparison run")
+    ap.add_argument("--compare-steps", type=int, default=600, help="c4: steps before the FP32-bulk error is taken")
+    ap.add_argument("--requests", type=int, default=24, help="c5: forecast requests")
+    ap.add_argument("--time-scale", type=float, default=30.0, help="c5: compression of arrivals and durations")
+    ap.add_argument("--chunk", type=int, default=200, help="c5: batch steps between admission points")
+    ap.add_argument("--hbm-gib", type=float, default=0.0, help="c5: HBM budget (default 80%% of free memory)")
+    ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "c5":
+        return bench_serve(args)
+    if args.config == "c4":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "fp32-bulk"          # the ensemble runs in FP32-bulk unless asked otherwise
+        return bench_batch(args)
 
     import numpy as np
     import torch

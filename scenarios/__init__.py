@@ -253,6 +253,106 @@ def c3(scale: int = 1, seed: int = 3) -> Scenario:
 
 
 # ---------------------------------------------------------------------------
+def _single(seed: int, n: int, amp: float) -> Scenario:
+    """One level of n x n cells at 810 m over a C1-style shelf (6000 m deep in
+    the west, 50 m of land in the east, 8 shoals), dt = 1 s, with an elliptic
+    uplift of amplitude amp in the deep half."""
+    rng = np.random.default_rng(seed)
+    dx = 810.0
+    L = n * dx
+    sc = Scenario(f"single-{n}", [_level(n, n)], dx0=dx, dt=1.0, steps=0)
+    X, Y = sc.cell_centres(0)
+    h = 6000.0 - 6050.0 * X / L
+    for _ in range(8):
+        cx, cy = rng.uniform(0, L, size=2)
+        h = h - 200.0 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * 10e3 ** 2))
+    sc.levels[0]["h"] = np.ascontiguousarray(h)
+    xc, yc = rng.uniform(0.15 * L, 0.55 * L), rng.uniform(0.2 * L, 0.8 * L)
+    sc.source = Source(xc, yc, 50e3, 25e3, rng.uniform(0, math.pi), amp, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+def _nest3(seed: int, cells: float, amp: float) -> Scenario:
+    """Three nested levels (810/270/90 m) in the proportions of the first
+    three C2 levels (1200x1000, 900^2, 1500^2), scaled to about `cells`
+    cells, over a seeded wavy coast, dt = 0.2 s, elliptic uplift of amplitude
+    amp about 150 km (scaled) offshore."""
+    rng = np.random.default_rng(seed)
+    f = math.sqrt(cells / (1200 * 1000 + 900 ** 2 + 1500 ** 2))
+    dx0 = 810.0
+    nx0, ny0 = int(round(1200 * f)), int(round(1000 * f))
+    n2 = 3 * int(round(300 * f))
+    n3 = 3 * int(round(500 * f))
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    X0 = 0.75 * Lx
+    coast = _Coast(rng, X0, Ly, wiggle=8e3 * f,
+                   knots=[(0.0, 0.0), (20e3 * f, 100.0), (60e3 * f, 1000.0), (200e3 * f, 5000.0), (1e9, 5000.0)],
+                   zmax=30.0, slope=30.0 / (6e3 * f), Lx=Lx, nbumps=6, scale=1.0 / f)
+    sc = Scenario(f"nest3-{nx0 * ny0 + n2 * n2 + n3 * n3}", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=0)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    _nest_chain(sc, [(n2, n2), (n3, n3)], (cx, cy), land_shift=[0.0, 0.0, 0.0])
+    _fill_depths(sc, coast)
+    sc.source = Source(cx - 150e3 * f, cy + rng.uniform(-0.2, 0.2) * Ly, 50e3 * f, 25e3 * f,
+                       0.5 * math.pi + rng.uniform(-0.3, 0.3), amp, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+def c4(count: int = 48, seed: int = 4000):
+    """The batched ensemble: `count` uneven scenarios, member s seeded with
+    seed + s.  Even members: one level of n^2 cells, n log-uniform in
+    [256, 2048]; odd members: three nested levels of 1 M to 8 M cells
+    (log-uniform).  Uplift amplitudes uniform in [0.5, 5] m."""
+    out = []
+    for s in range(count):
+        rng = np.random.default_rng(seed + s)
+        amp = float(rng.uniform(0.5, 5.0))
+        if s % 2 == 0:
+            n = int(round(256 * 2.0 ** (3.0 * rng.uniform()) / 4)) * 4
+            sc = _single(seed + s, n, amp)
+        else:
+            sc = _nest3(seed + s, 1e6 * 8.0 ** rng.uniform(), amp)
+        sc.name = f"c4-{s:02d}-{sc.name}"
+        out.append(sc)
+    return out
+
+
+def c5_sites():
+    """The forecast-serving site database: six nested domains of 1 M to 47 M
+    cells (three-level nests of about 1, 2.5 and 6 M cells, C2, a 20 M
+    three-level nest and C3)."""
+    return [_nest3(5001, 1.0e6, 1.0), _nest3(5002, 2.5e6, 1.0), _nest3(5003, 6.0e6, 1.0), c2(),
+            _nest3(5004, 2.0e7, 1.0), c3()]
+
+
+def c5_requests(sites, count: int = 24, seed: int = 5000, rate_per_min: float = 2.0, time_scale: float = 30.0):
+    """Poisson arrivals (mean rate_per_min requests per minute) of forecast
+    requests: a site drawn uniformly, a simulated duration uniform in 1-6 h,
+    an uplift of 0.5-5 m shifted around the site's source.  time_scale
+    compresses both the arrival clock and the durations by the same factor
+    (30: 2 requests per minute become 1 per second, 1-6 h become 2-12 min),
+    so a serving run fits in a bench.  Returns (site index, source tuple,
+    steps, arrival seconds) per request."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(count):
+        t += rng.exponential(60.0 / rate_per_min) / time_scale
+        k = int(rng.integers(len(sites)))
+        sc = sites[k]
+        hours = rng.uniform(1.0, 6.0)
+        steps = max(1, int(round(hours * 3600.0 / time_scale / sc.dt)))
+        s0 = sc.source
+        Ly = sc.levels[0]["ny"] * sc.dx0
+        src = (s0.xc + rng.uniform(-0.05, 0.05) * Ly, s0.yc + rng.uniform(-0.15, 0.15) * Ly, s0.a, s0.b,
+               s0.theta + rng.uniform(-0.3, 0.3), float(rng.uniform(0.5, 5.0)), s0.shape)
+        out.append((k, src, steps, t))
+    return out
+
+
+# ---------------------------------------------------------------------------
 def small_nested(seed: int = 7, nlev: int = 3, base=(36, 30), child=(27, 27), dx0=810.0, dt=0.2,
                  bc=(BC_OPEN,) * 4) -> Scenario:
     """A small chain of nests over a random coast, for step-level tests.
