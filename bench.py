@@ -140,11 +140,14 @@ def bench_batch(args):
     batch.step(args.warmup)
     batch.sync()
     stream = batch.stream
+    all0, comp0 = batch.cell_updates()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    all1, comp1 = batch.cell_updates()
+    assert all1 - all0 == cells * steps
     log(f"timed {steps} batch steps: {wall:.3f} s")
     fused_ms, active_ms, prof_cells = batch.profile(args.profile_steps)
     bpc = BYTES_PER_CELL_FP32_BULK["k_fused"] if prec == RTI_FP32_BULK else BYTES_PER_CELL["k_fused"]
@@ -185,6 +188,8 @@ def bench_batch(args):
             "tile_rows": rows,
             "persistent": bool(args.persistent),
             "timed_steps_from": args.warmup,
+            "computed_cell_updates": comp1 - comp0,
+            "active_cell_updates_per_s": (comp1 - comp0) / wall,
         },
         "roofline": {
             "bound": "hbm", "kernel": "k_fused_batch", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -354,6 +359,7 @@ def main():
 
     stream = d.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    all0, comp0 = d.cell_updates()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -363,6 +369,8 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
     log(f"timed {steps} steps: {wall:.3f} s wall, {ev_ms / 1e3:.3f} s by events")
+    all1, comp1 = d.cell_updates()
+    assert all1 - all0 == sc.cells * steps
     e_last = d.get_state(len(sc.levels) - 1)[0]
     assert np.all(np.isfinite(e_last)), "non-finite state after the timed run"
     active, total, active_cells = d.active_tiles()
@@ -402,6 +410,8 @@ def main():
             "simulated_s": steps * sc.dt,
             "active_tiles": [active, total],
             "active_cells_last_step": active_cells,
+            "computed_cell_updates": comp1 - comp0,
+            "active_cell_updates_per_s": (comp1 - comp0) / wall,
             "flags": args.flags,
         },
         "roofline": {

@@ -187,6 +187,12 @@ int rti_profile(rti_domain *dom, int64_t nsteps, double *ms, const char **names,
  * tile counts as computed.  Synchronises. */
 int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *active_cells);
 
+/* Cell-updates of the steps this domain took through its own launches
+ * (rti_step, rti_run, rti_profile; not through a batch): *all counts every
+ * cell of every level at every step, *computed only the cells of the tiles
+ * the fused kernel computed (quiescent dry tiles skipped).  Synchronises. */
+int rti_cell_updates(rti_domain *dom, int64_t *all, int64_t *computed);
+
 /* Tile shape of the fused kernel.  A tile is 60 columns wide and `rows` rows
  * high, rows in [RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX] (default
  * RTI_TILE_ROWS_DEFAULT).  The tile shape changes only the work decomposition:
@@ -241,6 +247,10 @@ int rti_batch_sync(rti_batch *batch);
  * average fused-kernel and active-list-kernel durations per launch [ms] and
  * the average number of cells in the tiles computed per step.  Synchronises. */
 int rti_batch_profile(rti_batch *batch, int64_t nsteps, double *fused_ms, double *active_ms, double *active_cells);
+
+/* Cell-updates of every batch step since the batch was created (as
+ * rti_cell_updates, summed over the members).  Synchronises. */
+int rti_batch_cell_updates(rti_batch *batch, int64_t *all, int64_t *computed);
 
 /* Free the batch's tables and graphs; the members stay valid (and can be
  * stepped alone again).  NULL is a no-op.  Synchronises first. */

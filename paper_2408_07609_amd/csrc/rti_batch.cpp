@@ -34,6 +34,8 @@ struct rti_batch {
     bool dirty = true;
     int flip = 0;                        // parity of the next step relative to par
     int64_t steps = 0;                   // batch steps since the tables were built
+    unsigned long long cells_done = 0;   // computed cells carried over when the tables are rebuilt
+    int64_t cell_updates_all = 0;        // every member's cells times the steps it took in the batch
 };
 
 namespace {
@@ -67,6 +69,8 @@ bool stale(const rti_batch *B)
 int build_tables(rti_batch *B)
 {
     HIP_TRY(hipStreamSynchronize(B->stream));
+    if (B->mem)   // carry the computed-cells counter over to the new tables
+        HIP_TRY(hipMemcpy(&B->cells_done, B->dev.cells_done, sizeof B->cells_done, hipMemcpyDeviceToHost));
     drop_graphs(B);
     const int n = (int)B->members.size();
     B->base.assign(n + 1, 0);
@@ -107,7 +111,8 @@ int build_tables(rti_batch *B)
     if (ntiles)
         HIP_TRY(hipMemcpyAsync(p + o_tdom, B->tdom.data(), sizeof(uint16_t) * ntiles, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_par, par.data(), (size_t)n, hipMemcpyHostToDevice, B->stream));
-    HIP_TRY(hipMemsetAsync(p + o_count, 0, kAlign, B->stream));
+    HIP_TRY(hipMemsetAsync(p + o_count, 0, 16, B->stream));                  // list counters
+    HIP_TRY(hipMemcpyAsync(p + o_count + 16, &B->cells_done, sizeof B->cells_done, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));   // host vectors die on return
     BatchDev &bd = B->dev;
     bd.doms = reinterpret_cast<const DomainDev *>(p + o_doms);
@@ -116,6 +121,7 @@ int build_tables(rti_batch *B)
     bd.par = reinterpret_cast<const uint8_t *>(p + o_par);
     bd.list = reinterpret_cast<int32_t *>(p + o_list);
     bd.count = reinterpret_cast<int32_t *>(p + o_count);
+    bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_count + 16);
     bd.n = n;
     bd.ntiles = ntiles;
     B->flip = 0;
@@ -162,6 +168,9 @@ void advance(rti_batch *B, int64_t n)
     for (rti_domain *D : B->members) {
         D->steps += n;
         D->cur ^= (int)(n & 1);
+        int64_t cells = 0;
+        for (const auto &p : D->plan.lv) cells += (int64_t)p.nx * p.ny;
+        B->cell_updates_all += cells * n;
     }
     B->steps += n;
 }
@@ -363,6 +372,19 @@ int rti_batch_profile(rti_batch *B, int64_t nsteps, double *fused_ms, double *ac
     } catch (...) {
         return fail(RTI_EINVAL, "unexpected exception");
     }
+}
+
+int rti_batch_cell_updates(rti_batch *B, int64_t *all, int64_t *computed)
+{
+    if (!B || !all || !computed) return fail(RTI_EINVAL, "NULL argument");
+    unsigned long long done = B->cells_done;
+    if (B->mem) {   // the device counter stays current until the tables are rebuilt
+        HIP_TRY(hipMemcpyAsync(&done, B->dev.cells_done, sizeof done, hipMemcpyDeviceToHost, B->stream));
+        HIP_TRY(hipStreamSynchronize(B->stream));
+    }
+    *all = B->cell_updates_all;
+    *computed = (int64_t)done;
+    return RTI_OK;
 }
 
 void rti_batch_destroy(rti_batch *B)

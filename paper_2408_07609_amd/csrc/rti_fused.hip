@@ -200,8 +200,8 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
     const int l = level_of_tile(d, g);
     const LevelDev &L = d.lv[l];
     const int tl = g - L.tile_base;
-    const int x0 = (tl % L.tiles_x) * RTI_TW;
-    const int y0 = (tl / L.tiles_x) * d.th;
+    const int x0 = tile_x(tl, L.tiles_x, L.tiles_y) * RTI_TW;
+    const int y0 = tile_y(tl, L.tiles_x, L.tiles_y) * d.th;
     const uint8_t info = d.tinfo[g];
     const bool has_child = (info & TI_CHILD) != 0;
     const bool root = (l == 0);
@@ -461,7 +461,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
     const int l = level_of_tile(d, g);
     const LevelDev &L = d.lv[l];
     const int tl = g - L.tile_base;
-    const int tx = tl % L.tiles_x, ty = tl / L.tiles_x;
+    const int tx = tile_x(tl, L.tiles_x, L.tiles_y), ty = tile_y(tl, L.tiles_x, L.tiles_y);
     unsigned acc = 3u;
     #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
@@ -469,7 +469,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
         for (int dx = -1; dx <= 1; ++dx) {
             const int x = tx + dx, y = ty + dy;
             const bool in = x >= 0 && x < L.tiles_x && y >= 0 && y < L.tiles_y;
-            const unsigned f = in ? (unsigned)d.tflag[L.tile_base + y * L.tiles_x + x] : 3u;
+            const unsigned f = in ? (unsigned)d.tflag[L.tile_base + tile_index(x, y, L.tiles_x, L.tiles_y)] : 3u;
             acc &= f;
         }
     }
@@ -506,10 +506,18 @@ __device__ __forceinline__ void append_active(int a, int id, int *count_b, int *
     if (a) list[base + before + incl - 1] = id;
 }
 
+// Sum of c over the wavefront added to *total (one atomic per wavefront).
+__device__ __forceinline__ void add_cells(int c, unsigned long long *total)
+{
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
+}
+
 __global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)
 {
     const int g = (int)blockIdx.x * 256 + (int)threadIdx.x;
     const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
+    add_cells(a ? d.tcells[g] : 0, d.cells_done);
     append_active(a, g, &d.count[b], &d.count[b ^ 1], d.list);
 }
 
@@ -517,11 +525,14 @@ __global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_acti
 __global__ __launch_bounds__(256) void k_active_batch(BatchDev bd, int flip, int all_active)
 {
     const int G = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    int a = 0;
+    int a = 0, c = 0;
     if (G < bd.ntiles) {
         const int m = bd.tdom[G];
-        a = tile_active(bd.doms[m], G - bd.base[m], all_active);
+        const DomainDev &d = bd.doms[m];
+        a = tile_active(d, G - bd.base[m], all_active);
+        c = a ? d.tcells[G - bd.base[m]] : 0;
     }
+    add_cells(c, bd.cells_done);
     append_active(a, G, &bd.count[flip], &bd.count[flip ^ 1], bd.list);
 }
 

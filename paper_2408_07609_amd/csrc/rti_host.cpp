@@ -66,9 +66,10 @@ void plan_tiles(Plan &plan, int th)
                     const bool inside_inner = ax >= fx0 + 3 && bx <= fx1 - 3 && ay >= fy0 + 3 && by <= fy1 - 3;
                     if (meets_outer && !inside_inner) bits |= TI_CHILD | TI_PINNED;
                 }
-                plan.tinfo[base + ty * p.tiles_x + tx] = bits;
+                const int g = base + tile_index(tx, ty, p.tiles_x, p.tiles_y);
+                plan.tinfo[g] = bits;
                 const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
-                plan.tcells[base + ty * p.tiles_x + tx] = std::max(0, w) * std::max(0, hgt);
+                plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
             }
         }
         base += p.tiles_x * p.tiles_y;
@@ -184,8 +185,8 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     plan.level_bytes = bytes;
     plan_tiles(plan, RTI_TH_MIN);             // the most tiles any height gives
     const int cap = plan.ntiles;
-    // tile info, tile flags, active list, control block (count, divergence flag)
-    bytes += 2 * align_up((size_t)cap, kAlign) + align_up((size_t)cap * 4, kAlign) + kAlign;
+    // tile info, tile flags, active list, tile cells, control block (counts, divergence flag, cells done)
+    bytes += 2 * align_up((size_t)cap, kAlign) + 2 * align_up((size_t)cap * 4, kAlign) + kAlign;
     plan.bytes = bytes;
     plan.ntiles_cap = cap;
     plan.s_ntiles = s_ntiles;
@@ -221,8 +222,11 @@ int carve(rti_domain *D)
     D->dev.tinfo = D->tinfo;
     D->dev.tflag = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.list = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
+    D->tcells = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
+    D->dev.tcells = D->tcells;
     D->ctrl = reinterpret_cast<int *>(take(kAlign));
-    D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity
+    D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity, ctrl[2] divergence flag
+    D->dev.cells_done = reinterpret_cast<unsigned long long *>(D->ctrl + 4);   // bytes 16..23
     return RTI_OK;
 }
 
@@ -388,6 +392,8 @@ int retile(rti_domain *D, int th)
         base += p.tiles_x * p.tiles_y;
     }
     HIP_TRY(hipMemcpyAsync(D->tinfo, D->plan.tinfo.data(), D->plan.tinfo.size(), hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipMemcpyAsync(D->tcells, D->plan.tcells.data(), D->plan.tcells.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, D->stream));
     int rc = forget_quiet(D);
     if (!rc) rc = reset_counts(D);
     if (rc) return rc;
@@ -535,6 +541,9 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         e = hipMemsetAsync(D->mem, 0, plan.bytes, D->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(D->tinfo, plan.tinfo.data(), plan.tinfo.size(), hipMemcpyHostToDevice, D->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(D->tcells, plan.tcells.data(), plan.tcells.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, D->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(D->stream);
         if (e != hipSuccess) {
             rti_domain_destroy(D);
@@ -652,12 +661,14 @@ int rti_step(rti_domain *D, int64_t nsteps)
                 }
                 HIP_TRY(hipGraphLaunch(D->exec[D->cur], D->stream));
                 D->steps += kGraphSteps;
+                D->own_steps += kGraphSteps;
                 nsteps -= kGraphSteps;
             } else {
                 int rc = launch_step(D, D->cur, D->stream);
                 if (rc) return rc;
                 D->cur ^= 1;
                 D->steps += 1;
+                D->own_steps += 1;
                 nsteps -= 1;
             }
         }
@@ -810,6 +821,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
         }
         D->cur ^= 1;
         D->steps += 1;
+        D->own_steps += 1;
         if (avg_cells) {
             int64_t t = 0, c = 0;
             if ((rc = active_cells(D, &t, &c))) break;
@@ -836,6 +848,19 @@ int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total, int64_t *ce
     int rc = active_cells(D, active, cells);
     if (rc) return rc;
     *total = (D->flags & RTI_FLAG_PHASED) ? D->dev.s_ntiles : D->dev.ntiles;
+    return RTI_OK;
+}
+
+int rti_cell_updates(rti_domain *D, int64_t *all, int64_t *computed)
+{
+    if (!D || !all || !computed) return fail(RTI_EINVAL, "NULL argument");
+    int64_t cells = 0;
+    for (const auto &p : D->plan.lv) cells += (int64_t)p.nx * p.ny;
+    unsigned long long done = 0;
+    HIP_TRY(hipMemcpyAsync(&done, D->dev.cells_done, sizeof done, hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    *all = cells * D->own_steps;
+    *computed = (D->flags & RTI_FLAG_PHASED) ? *all : (int64_t)done;
     return RTI_OK;
 }
 
@@ -873,17 +898,20 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
     hipEvent_t ev[2] = {nullptr, nullptr};
     const int cur0 = D->cur;
     const int64_t steps0 = D->steps;
+    unsigned long long done0 = 0;           // the trials do not count as computed cells
     int best = D->plan.th;
     double best_ms = 0.0;
     int rc = RTI_OK;
     auto restore = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice, D->stream));
+        HIP_TRY(hipMemcpyAsync(D->dev.cells_done, &done0, sizeof done0, hipMemcpyHostToDevice, D->stream));
         D->cur = cur0;
         D->steps = steps0;
         int rc2 = forget_quiet(D);
         return rc2 ? rc2 : reset_counts(D);
     };
     try {
+        HIP_TRY(hipMemcpyAsync(&done0, D->dev.cells_done, sizeof done0, hipMemcpyDeviceToHost, D->stream));
         HIP_TRY(hipStreamSynchronize(D->stream));
         hipError_t e = hipMalloc(&snap, D->plan.level_bytes);
         if (e != hipSuccess) return fail(RTI_ENOMEM, "autotune snapshot of %zu bytes: %s", D->plan.level_bytes, hipGetErrorString(e));
@@ -933,6 +961,7 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         // leave the domain as it was, whatever failed
         (void)hipStreamSynchronize(D->stream);
         (void)hipMemcpy(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice);
+        (void)hipMemcpy(D->dev.cells_done, &done0, sizeof done0, hipMemcpyHostToDevice);
         D->cur = cur0;
         D->steps = steps0;
         (void)forget_quiet(D);

@@ -34,6 +34,26 @@
 #define RTI_PAD_TOP (RTI_PD + 3)
 #define RTI_PAD_BOTTOM 3
 
+// Numbering of a level's fused-kernel tiles: RTI_TILE_ORDER 0 numbers them
+// row by row (x fastest), 1 column by column (y fastest).  The active list
+// keeps this order and each XCD takes a contiguous slice of it, so the order
+// decides which neighbouring tiles run close together in one L2.
+#ifndef RTI_TILE_ORDER
+#define RTI_TILE_ORDER 0
+#endif
+__host__ __device__ inline int tile_index(int tx, int ty, int tiles_x, int tiles_y)
+{
+    return RTI_TILE_ORDER ? tx * tiles_y + ty : ty * tiles_x + tx;
+}
+__host__ __device__ inline int tile_x(int tl, int tiles_x, int tiles_y)
+{
+    return RTI_TILE_ORDER ? tl / tiles_y : tl % tiles_x;
+}
+__host__ __device__ inline int tile_y(int tl, int tiles_x, int tiles_y)
+{
+    return RTI_TILE_ORDER ? tl % tiles_y : tl / tiles_x;
+}
+
 // Static per-tile bits (host-computed at create).
 #define TI_PINNED 0x1u      // never skipped and never reported quiescent
 #define TI_CHILD 0x2u       // the tile's extended region meets a child's ring or edge faces
@@ -74,6 +94,8 @@ struct DomainDev {
     uint8_t *tflag;                        // ntiles: bit0 quiescent after the last step, bit1 after the one before
     int32_t *list;                         // ntiles: active tiles of the current step
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
+    const int32_t *tcells;                 // ntiles: cells of the level inside each tile
+    unsigned long long *cells_done;        // cells of all computed tiles, summed over the steps
     LevelDev lv[RTI_MAX_LEVELS_DEV];
 };
 
@@ -88,6 +110,7 @@ struct BatchDev {
     int32_t n, ntiles;
     int32_t *list;                         // ntiles: active global tiles of the current step
     int32_t *count;                        // [flip]
+    unsigned long long *cells_done;        // cells of all computed tiles of all members, summed over the steps
 };
 
 // Kernel kinds (for profiling).

@@ -70,8 +70,10 @@ struct rti_domain {
     bool owns_mem = false;
     int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag
     uint8_t *tinfo = nullptr;
+    int32_t *tcells = nullptr;
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;
+    int64_t own_steps = 0;               // steps taken by this domain's own launches (not through a batch)
     uint32_t flags = 0;
     double dt = 0.0;
     bool diverged = false;

@@ -70,6 +70,9 @@ FUNCTIONS = {
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
     "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]),
+    "rti_cell_updates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "rti_batch_cell_updates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "rti_domain_set_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rti_domain_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "rti_domain_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
@@ -190,6 +193,20 @@ def rti_active_tiles(dom: int):
     a, t, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     _check(LIB.rti_active_tiles(dom, ctypes.byref(a), ctypes.byref(t), ctypes.byref(c)))
     return int(a.value), int(t.value), int(c.value)
+
+
+def rti_cell_updates(dom: int):
+    """Returns (all cell-updates, computed cell-updates) of the domain's own steps."""
+    a, c = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(LIB.rti_cell_updates(dom, ctypes.byref(a), ctypes.byref(c)))
+    return int(a.value), int(c.value)
+
+
+def rti_batch_cell_updates(batch: int):
+    """Returns (all cell-updates, computed cell-updates) of the batch's steps."""
+    a, c = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(LIB.rti_batch_cell_updates(batch, ctypes.byref(a), ctypes.byref(c)))
+    return int(a.value), int(c.value)
 
 
 def rti_domain_set_tile_rows(dom: int, rows: int):
@@ -371,6 +388,10 @@ class Domain:
     def active_tiles(self):
         return rti_active_tiles(self._h)
 
+    def cell_updates(self):
+        """(all, computed) cell-updates of this domain's own steps."""
+        return rti_cell_updates(self._h)
+
     # -- tile shape
     @property
     def tile_rows(self):
@@ -418,6 +439,10 @@ class Batch:
     def profile(self, nsteps):
         """(fused ms per launch, active-list ms per launch, cells computed per step)."""
         return rti_batch_profile(self._h, nsteps)
+
+    def cell_updates(self):
+        """(all, computed) cell-updates of the batch's steps."""
+        return rti_batch_cell_updates(self._h)
 
     def close(self):
         if getattr(self, "_h", None):

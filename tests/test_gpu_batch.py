@@ -189,3 +189,33 @@ def test_autotune_restores_state():
     assert_same(snapshot(d), before, "state after autotune")
     d.step(40)
     assert_same(snapshot(d), want, "run continued after autotune")
+
+
+def test_cell_update_counters():
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, Batch
+    sc = scenarios.c2(scale=10)
+    d = make(sc)
+    d.step(200)                              # graph-replayed steps count too
+    a0, c0 = d.cell_updates()
+    assert a0 == sc.cells * 200 and 0 < c0 <= a0
+    fused_avg_cells = d.profile(30)[1]       # eager steps, active cells read from each step's list
+    a1, c1 = d.cell_updates()
+    assert a1 - a0 == sc.cells * 30
+    assert abs((c1 - c0) - fused_avg_cells * 30) < 0.5
+    d.autotune(3)                            # the trials are not counted
+    assert d.cell_updates() == (a1, c1)
+    full = make(sc, flags=RTI_FLAG_NO_ACTIVE)
+    full.step(25)
+    assert full.cell_updates() == (sc.cells * 25, sc.cells * 25)
+    scs = members()[:3]
+    ds = [make(s) for s in scs]
+    with Batch(ds) as b:
+        b.step(40)
+        ba, bc = b.cell_updates()
+        assert ba == 40 * sum(s.cells for s in scs) and 0 < bc <= ba
+        avg = b.profile(10)[2]
+        ba2, bc2 = b.cell_updates()
+        assert abs((bc2 - bc) - avg * 10) < 0.5
+        b.add(make(members()[3]))            # the counter survives a rebuild of the tables
+        b.step(5)
+        assert b.cell_updates()[1] > bc2
