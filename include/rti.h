@@ -224,9 +224,12 @@ void rti_domain_destroy(rti_domain *dom);
  * fused launch per step over a global table of every member's tiles (uneven
  * sizes, level counts and tile heights mixed).  Each member keeps its own
  * state, parity and maxima; a member's results are bitwise the ones it gets
- * stepped alone.  Members must share the device, the precision and the
- * stream given here (hip_stream, borrowed), may not use RTI_FLAG_PHASED, and
- * belong to at most one batch.  While a domain is in a batch it is stepped
+ * stepped alone.  Members must share the device and the precision, may not
+ * use RTI_FLAG_PHASED, and belong to at most one batch.  Every batch kernel
+ * runs on hip_stream (borrowed).  A member created on another stream is
+ * adopted: rti_batch_add waits for the work queued on that stream, and while
+ * the domain is in the batch all of its calls run on the batch's stream; it
+ * returns to its own stream when it leaves.  While a domain is in a batch it is stepped
  * only through the batch (rti_step and rti_run on it return RTI_ESTATE);
  * reading its state, maxima and step count works as usual.  Members may be
  * added and removed between batch steps (continuous batching: a member added

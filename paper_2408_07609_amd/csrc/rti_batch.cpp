@@ -180,7 +180,6 @@ int check_member(const rti_batch *B, const rti_domain *D)
     if (!D) return fail(RTI_EINVAL, "member is NULL");
     if (D->batch) return fail(RTI_ESTATE, "the domain already belongs to a batch");
     if (D->device != B->device) return fail(RTI_EINVAL, "the domain lives on device %d, the batch on %d", D->device, B->device);
-    if (D->stream != B->stream) return fail(RTI_EINVAL, "the domain's stream differs from the batch's");
     if (D->flags & RTI_FLAG_PHASED) return fail(RTI_EINVAL, "members use the fused kernel (no RTI_FLAG_PHASED)");
     if (D->diverged) return fail(RTI_EDIVERGED, "the domain diverged earlier");
     if (B->bulk32 >= 0 && D->dev.bulk32 != B->bulk32) return fail(RTI_EINVAL, "members share one precision");
@@ -198,6 +197,7 @@ void rti_rt::batch_forget_member(rti_batch *B, rti_domain *D)
     D->batch = nullptr;
     (void)reset_counts(D);          // its parity moved under the batch
     (void)hipStreamSynchronize(B->stream);
+    D->stream = D->home_stream;
     B->dirty = true;
     drop_graphs(B);
 }
@@ -242,6 +242,12 @@ int rti_batch_add(rti_batch *B, rti_domain *D)
         if (!B) return fail(RTI_EINVAL, "batch is NULL");
         int rc = check_member(B, D);
         if (rc) return rc;
+        if (D->stream != B->stream) {
+            // adopt: the work queued on the member's own stream finishes first,
+            // then everything of the member runs on the batch's stream
+            HIP_TRY(hipStreamSynchronize(D->stream));
+            D->stream = B->stream;
+        }
         B->members.push_back(D);
         D->batch = B;
         B->bulk32 = D->dev.bulk32;
@@ -396,6 +402,7 @@ void rti_batch_destroy(rti_batch *B)
         (void)reset_counts(D);      // its parity moved under the batch
     }
     (void)hipStreamSynchronize(B->stream);
+    for (rti_domain *D : B->members) D->stream = D->home_stream;
     drop_graphs(B);
     if (B->capture) (void)hipStreamDestroy(B->capture);
     if (B->mem) (void)hipFree(B->mem);

@@ -321,6 +321,37 @@ int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &
     return RTI_OK;
 }
 
+// Initial state of level k computed on the device from the depth already
+// there: the lake at rest (src NULL) or the lake plus the source; fluxes zero.
+// Asynchronous on the domain's stream.
+int device_initial(rti_domain *D, int k, const rti_source *src)
+{
+    const LevelPlan &p = D->plan.lv[k];
+    LevelDev &L = D->dev.lv[k];
+    InitSource sp{};
+    sp.ox = p.ox;
+    sp.oy = p.oy;
+    sp.dx = p.dx;
+    sp.shape = -1;
+    if (src) {
+        sp.xc = src->xc;
+        sp.yc = src->yc;
+        sp.a = src->a;
+        sp.b = src->b;
+        sp.ct = std::cos(src->theta);
+        sp.st = std::sin(src->theta);
+        sp.amp = src->amp;
+        sp.shape = src->shape;
+    }
+    const size_t in = ((size_t)RTI_PAD_BOTTOM * p.pitch + 2) * D->plan.elem;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMemsetAsync(static_cast<char *>(L.M[b]) - in, 0, p.xf_bytes, D->stream));
+        HIP_TRY(hipMemsetAsync(static_cast<char *>(L.N[b]) - in, 0, p.yf_bytes, D->stream));
+    }
+    HIP_TRY(launch_init_level(L, D->dev.bulk32, sp, D->stream));
+    return RTI_OK;
+}
+
 int launch_step(rti_domain *D, int b, hipStream_t s)
 {
     if (D->flags & RTI_FLAG_PHASED) {
@@ -483,6 +514,7 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         rti_domain *D = new rti_domain;
         D->plan = plan;
         D->stream = static_cast<hipStream_t>(hip_stream);
+        D->home_stream = D->stream;
         D->flags = desc->flags;
         D->dt = desc->dt;
         hipError_t e = hipGetDevice(&D->device);
@@ -554,13 +586,13 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             rc = put_rows_b(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
             if (rc) { rti_domain_destroy(D); return rc; }
             // the lake at rest on the depth as the kernels see it (rounded to FP32 in FP32-bulk)
-            std::vector<double> h(desc->levels[k].h, desc->levels[k].h + (size_t)p.nx * p.ny);
-            if (plan.elem == sizeof(float))
-                for (double &v : h) v = (double)(float)v;
-            std::vector<double> eta(h.size());
-            for (size_t c = 0; c < eta.size(); ++c) eta[c] = (h[c] > 0.0) ? 0.0 : -h[c];
-            rc = install_initial(D, k, h.data(), eta);
+            rc = device_initial(D, k, nullptr);
             if (rc) { rti_domain_destroy(D); return rc; }
+        }
+        e = hipStreamSynchronize(D->stream);     // the caller's depth arrays may go once create returns
+        if (e != hipSuccess) {
+            rti_domain_destroy(D);
+            return fail(RTI_EHIP, "initialising the levels failed: %s", hipGetErrorString(e));
         }
         *out = D;
         return RTI_OK;
@@ -580,38 +612,13 @@ int rti_set_source(rti_domain *D, const rti_source *src)
         if (!(src->a > 0.0) || !(src->b > 0.0) || !std::isfinite(src->amp) || !std::isfinite(src->xc)
             || !std::isfinite(src->yc) || !std::isfinite(src->theta))
             return fail(RTI_EINVAL, "source scales must be positive and values finite");
-        const double ct = std::cos(src->theta), st = std::sin(src->theta);
+        HIP_TRY(hipStreamSynchronize(D->stream));
         for (int k = 0; k < D->dev.nlev; ++k) {
-            const LevelPlan &p = D->plan.lv[k];
-            std::vector<double> h((size_t)p.nx * p.ny), eta(h.size());
-            int rc = get_rows_b(D, h.data(), p.nx, D->dev.lv[k].h, p.pitch, p.ny);
-            if (rc) return rc;
-            HIP_TRY(hipStreamSynchronize(D->stream));
-            for (int j = 0; j < p.ny; ++j) {
-                for (int i = 0; i < p.nx; ++i) {
-                    const size_t c = (size_t)j * p.nx + i;
-                    const double x = p.ox + ((double)i + 0.5) * p.dx;
-                    const double y = p.oy + ((double)j + 0.5) * p.dx;
-                    const double ddx = x - src->xc, ddy = y - src->yc;
-                    const double xp = ddx * ct + ddy * st;
-                    const double yp = -(ddx * st) + ddy * ct;
-                    const double u = xp / src->a, v = yp / src->b;
-                    const double rho2 = u * u + v * v;
-                    double s;
-                    if (src->shape == RTI_GAUSS) {
-                        s = src->amp * std::exp(-0.5 * rho2);
-                    } else if (rho2 < 1.0) {
-                        const double cs = std::cos(0.5 * M_PI * std::sqrt(rho2));
-                        s = src->amp * (cs * cs);
-                    } else {
-                        s = 0.0;
-                    }
-                    eta[c] = (h[c] > 0.0) ? s : -h[c];
-                }
-            }
-            rc = install_initial(D, k, h.data(), eta);
+            int rc = device_initial(D, k, src);
             if (rc) return rc;
         }
+        int rc = forget_quiet(D);
+        if (rc) return rc;
         D->steps = 0;
         D->diverged = false;
         return RTI_OK;

@@ -113,6 +113,15 @@ struct BatchDev {
     unsigned long long *cells_done;        // cells of all computed tiles of all members, summed over the steps
 };
 
+// Parameters of the initial state of one level: the level's origin and
+// spacing, and the source (shape -1: none, the lake at rest; 0 Gaussian;
+// 1 cos^2 ellipse), its rotation given as cos/sin.
+struct InitSource {
+    double ox, oy, dx;
+    double xc, yc, a, b, ct, st, amp;
+    int32_t shape;
+};
+
 // Kernel kinds (for profiling).
 enum {
     K_MASS = 0, K_JNZ, K_MOMENTUM, K_JNQ, K_FUSED, K_ACTIVE, K_FINITE, K_NKINDS
@@ -125,6 +134,7 @@ hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+hipError_t launch_init_level(const LevelDev &L, int bulk32, const InitSource &sp, hipStream_t s);
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s);
 hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
 hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, hipStream_t s);

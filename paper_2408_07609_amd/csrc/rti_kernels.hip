@@ -285,6 +285,42 @@ int max_edge(const DomainDev &d)
     return m;
 }
 
+// Initial state of one level at t = 0: water level from the depth (and the
+// source, when shape >= 0), both eta buffers and the maxima.  Sea cells (h > 0)
+// take the displacement of the source (paper Sec. IV-A input; the shapes of
+// rti_source), land keeps eta = -h, and a level below the ground is clipped
+// to it; the maxima start at the initial values (sea: eta, land: h + eta).
+template <typename F>
+__global__ __launch_bounds__(256) void k_init_level(LevelDev L, InitSource sp)
+{
+    const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+    const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
+    if (i >= L.nx || j >= L.ny) return;
+    const int c = i + L.pitch * j;
+    const double h = (double)static_cast<const F *>(L.h)[c];
+    double s = 0.0;
+    if (sp.shape >= 0) {
+        const double x = sp.ox + ((double)i + 0.5) * sp.dx;
+        const double y = sp.oy + ((double)j + 0.5) * sp.dx;
+        const double ddx = x - sp.xc, ddy = y - sp.yc;
+        const double xp = ddx * sp.ct + ddy * sp.st;
+        const double yp = -(ddx * sp.st) + ddy * sp.ct;
+        const double u = xp / sp.a, v = yp / sp.b;
+        const double rho2 = u * u + v * v;
+        if (sp.shape == 0) {
+            s = sp.amp * exp(-0.5 * rho2);
+        } else if (rho2 < 1.0) {
+            const double cs = cos(0.5 * M_PI * sqrt(rho2));
+            s = sp.amp * (cs * cs);
+        }
+    }
+    double eta = (h > 0.0) ? s : -h;
+    if (h + eta < 0.0) eta = -h;
+    L.eta[0][c] = eta;
+    L.eta[1][c] = eta;
+    static_cast<F *>(L.zmax)[c] = (F)((h > 0.0) ? eta : h + eta);
+}
+
 }  // namespace
 
 hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s)
@@ -325,5 +361,15 @@ hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t
 hipError_t launch_zero_int(int *p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_level(const LevelDev &L, int bulk32, const InitSource &sp, hipStream_t s)
+{
+    const dim3 grid((L.nx + 63) / 64, (L.ny + 3) / 4);
+    if (bulk32)
+        hipLaunchKernelGGL(k_init_level<float>, grid, dim3(256), 0, s, L, sp);
+    else
+        hipLaunchKernelGGL(k_init_level<double>, grid, dim3(256), 0, s, L, sp);
     return hipGetLastError();
 }

@@ -62,7 +62,8 @@ struct rti_batch;
 struct rti_domain {
     rti_rt::Plan plan;
     DomainDev dev{};
-    hipStream_t stream = nullptr;        // borrowed
+    hipStream_t stream = nullptr;        // borrowed (the batch's stream while in a batch)
+    hipStream_t home_stream = nullptr;   // the stream given at create, restored on leaving a batch
     hipStream_t capture = nullptr;       // private, for graph capture
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};

@@ -408,8 +408,9 @@ class Domain:
 
 class Batch:
     """Domains stepped together by one launch per step over all their tiles.
-    Members must have been created on the stream given here (default: torch's
-    current stream) with one precision."""
+    Members share one precision; the batch runs on the stream given here
+    (default: torch's current stream) and adopts members created on other
+    streams while they belong to it."""
 
     def __init__(self, members=(), flags=0, device="cuda:0", stream=None):
         import torch

@@ -10,7 +10,9 @@ at its own step count.  A finished request's maxima (the forecast) are read
 back, its domain is removed from the batch and destroyed, and its footprint
 returns to the budget.  Requests that arrive while others are on the GPU
 therefore join the running launch between two chunks, and their work shares
-every launch with the others'.  All numerical work runs in librti's kernels;
+every launch with the others'.  A new request's domain is created and its
+source set on a staging stream while the current chunk runs, and the batch
+adopts it for the next chunk.  All numerical work runs in librti's kernels;
 this module only schedules.
 """
 from __future__ import annotations
@@ -79,6 +81,7 @@ class ForecastServer:
         self.keep_state = keep_state
         self.device = device
         self.stream = torch.cuda.current_stream(torch.device(device))
+        self.stage = torch.cuda.Stream(torch.device(device))   # new requests are prepared here
         self.batch = Batch([], device=device, stream=self.stream)
         self.used = 0
         self.peak_members = 0
@@ -89,9 +92,9 @@ class ForecastServer:
         from .rti import Domain
         s = req.site
         d = Domain(s.levels, s.dx0, s.dt, g=s.g, manning_n=s.manning_n, dry_eps=s.dry_eps, bc=s.bc, x0=s.x0, y0=s.y0,
-                   flags=self.flags, device=self.device, stream=self.stream, precision=self.precision)
+                   flags=self.flags, device=self.device, stream=self.stage, precision=self.precision)
         d.set_source(*req.source)
-        self.batch.add(d)
+        self.batch.add(d)       # waits for the staging stream only; the running chunk goes on
         return d
 
     def run(self, requests, clock=time.perf_counter, log=None):
@@ -107,10 +110,17 @@ class ForecastServer:
         results = []
         t0 = clock()
         while pending or waiting or active:
+            # 1. enqueue the next chunk for the running requests (asynchronous)
+            chunk = []
+            if active:
+                n = min(self.chunk, min(a[2] for a in active.values()))
+                self.batch.step(n)
+                chunk = list(active)
+                self.cell_updates += n * sum(a[0].site.cells for a in active.values())
+            # 2. while it runs: take in arrivals, admit in arrival order while the head fits
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admission in arrival order, while the head fits
             while waiting:
                 r = waiting[0]
                 need = footprint(r.site, self.precision, self.flags)
@@ -125,20 +135,15 @@ class ForecastServer:
                         f"{len(active)} running, {self.used / 2**30:.2f} GiB")
             self.peak_members = max(self.peak_members, len(active))
             self.peak_bytes = max(self.peak_bytes, self.used)
-            if not active:
-                if pending:
+            if not chunk:
+                if not active and pending:
                     time.sleep(max(0.0, min(0.05, pending[0].arrival - (clock() - t0))))
                 continue
-            n = min(self.chunk, min(a[2] for a in active.values()))
-            self.batch.step(n)
+            # 3. the chunk is done: retire the requests that reached their step count
             self.batch.sync()
-            self.cell_updates += n * sum(a[0].site.cells for a in active.values())
-            done = []
-            for rid, a in active.items():
-                a[2] -= n
-                if a[2] == 0:
-                    done.append(rid)
-            for rid in done:
+            for rid in chunk:
+                active[rid][2] -= n
+            for rid in [rid for rid in chunk if active[rid][2] == 0]:
                 r, d, _, need, admitted = active.pop(rid)
                 maxima = [d.max_inundation(k) for k in range(len(d.levels))]
                 res = Result(rid, r.site.cells, r.steps, r.arrival, admitted, clock() - t0, maxima)

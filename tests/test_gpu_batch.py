@@ -161,12 +161,6 @@ def test_batch_rules():
         with pytest.raises(RtiError) as ei:
             Batch([a])                     # one batch per domain
         assert ei.value.code == RTI_ESTATE
-        other = torch.cuda.Stream()
-        sc = scs[3]
-        d2 = Domain(sc.levels, sc.dx0, sc.dt, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc, stream=other)
-        with pytest.raises(RtiError) as ei:
-            batch.add(d2)                  # one stream per batch
-        assert ei.value.code == RTI_EINVAL
         batch.add(b)
         batch.step(3)
         b.close()                          # a destroyed member leaves the batch
@@ -219,3 +213,24 @@ def test_cell_update_counters():
         b.add(make(members()[3]))            # the counter survives a rebuild of the tables
         b.step(5)
         assert b.cell_updates()[1] > bc2
+
+
+def test_member_from_another_stream_is_adopted():
+    import torch
+    from paper_2408_07609_amd import Batch, Domain
+    sc = members()[3]
+    ref = make(sc)
+    ref.step(90)
+    other = torch.cuda.Stream()
+    d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
+               x0=sc.x0, y0=sc.y0, stream=other)
+    d.set_source(*sc.source.astuple())
+    d.step(21)                                # queued on its own stream
+    with Batch([make(members()[0])]) as b:
+        b.add(d)                              # waits for those steps, then runs on the batch's stream
+        b.step(40)
+        b.remove(d)
+    d.step(29)                                # back on its own stream
+    d.sync()
+    assert d.steps == 90
+    assert_same(snapshot(d), snapshot(ref), "adopted member")
