@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library drives one GPU)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -75,10 +75,12 @@ enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
 #define RTI_FLAG_PERSISTENT  0x8u   /* launch the fused kernel with a fixed grid of resident
                                        wavefronts that loop over the active tiles, instead of one
                                        workgroup per tile (also a flag of rti_batch_create) */
-#define RTI_MAX_LEVELS 16
+#define RTI_MAX_LEVELS 128
 
-/* One nest level.  Level 0 is the root (parent = -1); every other level names
- * a parent listed before it.  A child's spacing is its parent's divided by 3
+/* One nest level (a rectangular block of one resolution: a resolution that
+ * the paper's model covers with several blocks, Table 1, is several entries
+ * here, each with its own parent).  Level 0 is the root (parent = -1); every
+ * other level names a parent listed before it.  A child's spacing is its parent's divided by 3
  * (Sec. II-A); its nx and ny are multiples of 3 and at least 9; its footprint,
  * the parent cells [off_i, off_i + nx/3) x [off_j, off_j + ny/3), lies inside
  * the parent with at least 3 parent cells on every side; sibling footprints

@@ -35,6 +35,7 @@ struct rti_batch {
     int flip = 0;                        // parity of the next step relative to par
     int64_t steps = 0;                   // batch steps since the tables were built
     unsigned long long cells_done = 0;   // computed cells carried over when the tables are rebuilt
+    size_t nslot = 0;                    // computed-cell slots of the current tables
     int64_t cell_updates_all = 0;        // every member's cells times the steps it took in the batch
 };
 
@@ -66,11 +67,30 @@ bool stale(const rti_batch *B)
     return false;
 }
 
+// Sum of the computed-cell slots of the current tables (synchronises).
+int sum_cells(rti_batch *B, unsigned long long *out)
+{
+    std::vector<unsigned long long> part(B->nslot);
+    if (B->nslot) {
+        HIP_TRY(hipMemcpyAsync(part.data(), B->dev.cells_done, sizeof(unsigned long long) * B->nslot,
+                               hipMemcpyDeviceToHost, B->stream));
+        HIP_TRY(hipStreamSynchronize(B->stream));
+    }
+    unsigned long long t = 0;
+    for (auto v : part) t += v;
+    *out = t;
+    return RTI_OK;
+}
+
 int build_tables(rti_batch *B)
 {
     HIP_TRY(hipStreamSynchronize(B->stream));
-    if (B->mem)   // carry the computed-cells counter over to the new tables
-        HIP_TRY(hipMemcpy(&B->cells_done, B->dev.cells_done, sizeof B->cells_done, hipMemcpyDeviceToHost));
+    if (B->mem) {   // carry the computed-cells total over to the new tables
+        unsigned long long t = 0;
+        int rc = sum_cells(B, &t);
+        if (rc) return rc;
+        B->cells_done = t;
+    }
     drop_graphs(B);
     const int n = (int)B->members.size();
     B->base.assign(n + 1, 0);
@@ -96,7 +116,9 @@ int build_tables(rti_batch *B)
     const size_t o_par = o_tdom + align_up(sizeof(uint16_t) * std::max(ntiles, 1), kAlign);
     const size_t o_list = o_par + align_up((size_t)std::max(n, 1), kAlign);
     const size_t o_count = o_list + align_up(sizeof(int32_t) * std::max(ntiles, 1), kAlign);
-    const size_t bytes = o_count + kAlign;
+    const size_t nslot = (size_t)(std::max(ntiles, 1) + 255) / 256;      // one per active-list workgroup
+    const size_t o_cells = o_count + kAlign;
+    const size_t bytes = o_cells + align_up(sizeof(unsigned long long) * nslot, kAlign);
     if (bytes > B->mem_bytes) {
         if (B->mem) (void)hipFree(B->mem);
         B->mem = nullptr;
@@ -112,7 +134,8 @@ int build_tables(rti_batch *B)
         HIP_TRY(hipMemcpyAsync(p + o_tdom, B->tdom.data(), sizeof(uint16_t) * ntiles, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_par, par.data(), (size_t)n, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemsetAsync(p + o_count, 0, 16, B->stream));                  // list counters
-    HIP_TRY(hipMemcpyAsync(p + o_count + 16, &B->cells_done, sizeof B->cells_done, hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipMemsetAsync(p + o_cells, 0, sizeof(unsigned long long) * nslot, B->stream));
+    HIP_TRY(hipMemcpyAsync(p + o_cells, &B->cells_done, sizeof B->cells_done, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));   // host vectors die on return
     BatchDev &bd = B->dev;
     bd.doms = reinterpret_cast<const DomainDev *>(p + o_doms);
@@ -121,7 +144,8 @@ int build_tables(rti_batch *B)
     bd.par = reinterpret_cast<const uint8_t *>(p + o_par);
     bd.list = reinterpret_cast<int32_t *>(p + o_list);
     bd.count = reinterpret_cast<int32_t *>(p + o_count);
-    bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_count + 16);
+    bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_cells);
+    B->nslot = nslot;
     bd.n = n;
     bd.ntiles = ntiles;
     B->flip = 0;
@@ -384,9 +408,9 @@ int rti_batch_cell_updates(rti_batch *B, int64_t *all, int64_t *computed)
 {
     if (!B || !all || !computed) return fail(RTI_EINVAL, "NULL argument");
     unsigned long long done = B->cells_done;
-    if (B->mem) {   // the device counter stays current until the tables are rebuilt
-        HIP_TRY(hipMemcpyAsync(&done, B->dev.cells_done, sizeof done, hipMemcpyDeviceToHost, B->stream));
-        HIP_TRY(hipStreamSynchronize(B->stream));
+    if (B->mem) {   // the device slots stay current until the tables are rebuilt
+        int rc = sum_cells(B, &done);
+        if (rc) return rc;
     }
     *all = B->cell_updates_all;
     *computed = (int64_t)done;

@@ -126,7 +126,7 @@ template <typename F>
 __device__ double ring_level(const DomainDev &d, const LevelDev &L, int b, int c, int t, double e1, double hpar)
 {
     for (int q = 0; q < L.n_children; ++q) {
-        const LevelDev &C = d.lv[d.child[L.first_child + q]];
+        const LevelDev &C = level_of(d, child_level(d, L.first_child + q));
         const int I = c - C.off_i, J = t - C.off_j;
         const int fw = C.nx / 3, fh = C.ny / 3;
         if (I < 0 || J < 0 || I >= fw || J >= fh) continue;
@@ -162,7 +162,7 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
                              F Mnew, F Nnew)
 {
     for (int q = 0; q < L.n_children; ++q) {
-        const LevelDev &C = d.lv[d.child[L.first_child + q]];
+        const LevelDev &C = level_of(d, child_level(d, L.first_child + q));
         const int fw = C.nx / 3, fh = C.ny / 3;
         const int CP = C.pitch;
         if (xface && r >= C.off_j && r < C.off_j + fh && (c == C.off_i || c == C.off_i + fw)) {
@@ -184,13 +184,6 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
     }
 }
 
-__device__ __forceinline__ int level_of_tile(const DomainDev &d, int g)
-{
-    int l = 0;
-    for (int k = 1; k < d.nlev; ++k)
-        if (g >= d.lv[k].tile_base) l = k;
-    return l;
-}
 
 // One tile g of domain d: read buffer b, write buffer b^1 (paper Eqs. 1-3
 // and the nest exchanges of Sec. IV-C for the tile's cells and faces).
@@ -198,7 +191,7 @@ template <typename F>
 __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
 {
     const int l = level_of_tile(d, g);
-    const LevelDev &L = d.lv[l];
+    const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
     const int x0 = tile_x(tl, L.tiles_x, L.tiles_y) * RTI_TW;
     const int y0 = tile_y(tl, L.tiles_x, L.tiles_y) * d.th;
@@ -459,7 +452,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
     if (all_active) return 1;
     if (d.tinfo[g] & TI_PINNED) return 1;
     const int l = level_of_tile(d, g);
-    const LevelDev &L = d.lv[l];
+    const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
     const int tx = tile_x(tl, L.tiles_x, L.tiles_y), ty = tile_y(tl, L.tiles_x, L.tiles_y);
     unsigned acc = 3u;
@@ -506,11 +499,18 @@ __device__ __forceinline__ void append_active(int a, int id, int *count_b, int *
     if (a) list[base + before + incl - 1] = id;
 }
 
-// Sum of c over the wavefront added to *total (one atomic per wavefront).
-__device__ __forceinline__ void add_cells(int c, unsigned long long *total)
+// Sum of c over the workgroup added to this workgroup's own slot of part
+// (no atomics: each slot has one writer; the host adds the slots up).
+__device__ __forceinline__ void add_cells(int c, unsigned long long *part)
 {
+    __shared__ int csum[4];
     for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
+    if ((threadIdx.x & 63) == 0) csum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = (csum[0] + csum[1]) + (csum[2] + csum[3]);
+        if (t) part[blockIdx.x] += (unsigned long long)t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)

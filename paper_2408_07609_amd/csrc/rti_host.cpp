@@ -47,6 +47,7 @@ void plan_tiles(Plan &plan, int th)
     plan.ntiles = ntiles;
     plan.tinfo.assign(ntiles, 0);
     plan.tcells.assign(ntiles, 0);
+    plan.tlev.assign(ntiles, 0);
     const int nlev = (int)plan.lv.size();
     int base = 0;
     for (int l = 0; l < nlev; ++l) {
@@ -68,6 +69,7 @@ void plan_tiles(Plan &plan, int th)
                 }
                 const int g = base + tile_index(tx, ty, p.tiles_x, p.tiles_y);
                 plan.tinfo[g] = bits;
+                plan.tlev[g] = (uint8_t)l;
                 const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
                 plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
             }
@@ -91,6 +93,7 @@ int fused_grid(int ntiles, bool persistent, int cu_count)
 
 using namespace rti_rt;
 
+static_assert(RTI_MAX_LEVELS <= RTI_MAX_LEVELS_DEV && RTI_MAX_LEVELS <= 256, "level indices are stored in 8 bits");
 static_assert(RTI_TH == RTI_TILE_ROWS_DEFAULT && RTI_TH_MIN == RTI_TILE_ROWS_MIN && RTI_TH_MAX == RTI_TILE_ROWS_MAX,
               "tile heights of the ABI and the kernels disagree");
 
@@ -183,10 +186,18 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         bytes += 2 * p.eta_bytes + 2 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
     }
     plan.level_bytes = bytes;
+    plan.slev.clear();
+    for (int k = 0; k < (int)plan.lv.size(); ++k)
+        plan.slev.insert(plan.slev.end(), (size_t)plan.lv[k].s_tiles_x * plan.lv[k].s_tiles_y, (uint8_t)k);
     plan_tiles(plan, RTI_TH_MIN);             // the most tiles any height gives
     const int cap = plan.ntiles;
-    // tile info, tile flags, active list, tile cells, control block (counts, divergence flag, cells done)
-    bytes += 2 * align_up((size_t)cap, kAlign) + 2 * align_up((size_t)cap * 4, kAlign) + kAlign;
+    // tile info, tile flags, active list, tile cells, control block (counts, divergence flag),
+    // computed-cell sums (one per active-list workgroup)
+    bytes += 2 * align_up((size_t)cap, kAlign) + 2 * align_up((size_t)cap * 4, kAlign) + kAlign
+             + align_up(sizeof(unsigned long long) * (size_t)((cap + 255) / 256), kAlign);
+    // level table, child list, tile levels, per-phase tile levels
+    bytes += align_up(sizeof(LevelDev) * plan.lv.size(), kAlign) + align_up(sizeof(int32_t) * plan.lv.size(), kAlign)
+             + align_up((size_t)cap, kAlign) + align_up((size_t)s_ntiles, kAlign);
     plan.bytes = bytes;
     plan.ntiles_cap = cap;
     plan.s_ntiles = s_ntiles;
@@ -204,7 +215,7 @@ int carve(rti_domain *D)
     auto take = [&p](size_t n) { char *q = p; p += n; return q; };
     for (int k = 0; k < (int)D->plan.lv.size(); ++k) {
         const LevelPlan &pl = D->plan.lv[k];
-        LevelDev &L = D->dev.lv[k];
+        LevelDev &L = D->lvh[k];
         // base pointer = cell (0,0): RTI_PAD_BOTTOM padding rows and 2 padding columns in
         const size_t in = (size_t)RTI_PAD_BOTTOM * pl.pitch + 2;
         auto based = [&](size_t bytes, size_t elem) { return take(bytes) + in * elem; };
@@ -226,7 +237,17 @@ int carve(rti_domain *D)
     D->dev.tcells = D->tcells;
     D->ctrl = reinterpret_cast<int *>(take(kAlign));
     D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity, ctrl[2] divergence flag
-    D->dev.cells_done = reinterpret_cast<unsigned long long *>(D->ctrl + 4);   // bytes 16..23
+    D->dev.cells_done = reinterpret_cast<unsigned long long *>(
+        take(align_up(sizeof(unsigned long long) * ((nt + 255) / 256), kAlign)));
+    const size_t nl = D->plan.lv.size();
+    D->lv_dev = reinterpret_cast<LevelDev *>(take(align_up(sizeof(LevelDev) * nl, kAlign)));
+    D->child_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * nl, kAlign)));
+    D->tlev_dev = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
+    D->slev_dev = reinterpret_cast<uint8_t *>(take(align_up((size_t)D->plan.s_ntiles, kAlign)));
+    D->dev.lv = D->lv_dev;
+    D->dev.child = D->child_dev;
+    D->dev.tlev = D->tlev_dev;
+    D->dev.slev = D->slev_dev;
     return RTI_OK;
 }
 
@@ -299,7 +320,7 @@ namespace {
 int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &eta)
 {
     const LevelPlan &p = D->plan.lv[k];
-    LevelDev &L = D->dev.lv[k];
+    LevelDev &L = D->lvh[k];
     const size_t n = (size_t)p.nx * p.ny;
     std::vector<double> z(n);
     for (size_t c = 0; c < n; ++c) {
@@ -327,7 +348,7 @@ int install_initial(rti_domain *D, int k, const double *h, std::vector<double> &
 int device_initial(rti_domain *D, int k, const rti_source *src)
 {
     const LevelPlan &p = D->plan.lv[k];
-    LevelDev &L = D->dev.lv[k];
+    LevelDev &L = D->lvh[k];
     InitSource sp{};
     sp.ox = p.ox;
     sp.oy = p.oy;
@@ -396,6 +417,20 @@ int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
     return RTI_OK;
 }
 
+// The level table, child list and per-tile level indices to the device.
+int upload_tables(rti_domain *D)
+{
+    const size_t nl = D->lvh.size();
+    HIP_TRY(hipMemcpyAsync(D->lv_dev, D->lvh.data(), sizeof(LevelDev) * nl, hipMemcpyHostToDevice, D->stream));
+    if (!D->childh.empty())
+        HIP_TRY(hipMemcpyAsync(D->child_dev, D->childh.data(), sizeof(int32_t) * D->childh.size(),
+                               hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipMemcpyAsync(D->tlev_dev, D->plan.tlev.data(), D->plan.tlev.size(), hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipMemcpyAsync(D->slev_dev, D->plan.slev.data(), D->plan.slev.size(), hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));   // the host vectors may change after return
+    return RTI_OK;
+}
+
 void drop_graphs(rti_domain *D)
 {
     for (int p = 0; p < 2; ++p) {
@@ -417,11 +452,13 @@ int retile(rti_domain *D, int th)
     int base = 0;
     for (int k = 0; k < dv.nlev; ++k) {
         const LevelPlan &p = D->plan.lv[k];
-        dv.lv[k].tiles_x = p.tiles_x;
-        dv.lv[k].tiles_y = p.tiles_y;
-        dv.lv[k].tile_base = base;
+        D->lvh[k].tiles_x = p.tiles_x;
+        D->lvh[k].tiles_y = p.tiles_y;
+        D->lvh[k].tile_base = base;
         base += p.tiles_x * p.tiles_y;
     }
+    int rc0 = upload_tables(D);
+    if (rc0) return rc0;
     HIP_TRY(hipMemcpyAsync(D->tinfo, D->plan.tinfo.data(), D->plan.tinfo.size(), hipMemcpyHostToDevice, D->stream));
     HIP_TRY(hipMemcpyAsync(D->tcells, D->plan.tcells.data(), D->plan.tcells.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, D->stream));
@@ -543,10 +580,12 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         dv.bulk32 = (desc->precision == RTI_FP32_BULK) ? 1 : 0;
         dv.g = desc->g;
         dv.fc = 0.5 * desc->dt * desc->g * desc->manning_n * desc->manning_n;
+        D->lvh.assign(dv.nlev, LevelDev{});
+        D->childh.assign(dv.nlev, 0);
         int base = 0, sbase = 0;
         for (int k = 0; k < dv.nlev; ++k) {
             const LevelPlan &p = plan.lv[k];
-            LevelDev &L = dv.lv[k];
+            LevelDev &L = D->lvh[k];
             L.nx = p.nx; L.ny = p.ny; L.pitch = p.pitch;
             L.parent = p.parent; L.off_i = p.off_i; L.off_j = p.off_j;
             L.tiles_x = p.tiles_x; L.tiles_y = p.tiles_y; L.tile_base = base;
@@ -559,15 +598,20 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         {
             int nc = 0;
             for (int p = 0; p < dv.nlev; ++p) {
-                dv.lv[p].first_child = nc;
-                dv.lv[p].n_children = 0;
+                D->lvh[p].first_child = nc;
+                D->lvh[p].n_children = 0;
                 for (int k = p + 1; k < dv.nlev; ++k) {
                     if (desc->levels[k].parent == p) {
-                        dv.child[nc++] = k;
-                        dv.lv[p].n_children += 1;
+                        D->childh[nc++] = k;
+                        D->lvh[p].n_children += 1;
                     }
                 }
             }
+        }
+        for (int c = 1; c < dv.nlev; ++c) {
+            const int fw = plan.lv[c].nx / 3, fh = plan.lv[c].ny / 3;
+            dv.max_ring = std::max(dv.max_ring, 2 * fw + 2 * (fh - 2));
+            dv.max_edge = std::max(dv.max_edge, 2 * plan.lv[c].nx + 2 * plan.lv[c].ny);
         }
         carve(D);
         e = hipMemsetAsync(D->mem, 0, plan.bytes, D->stream);
@@ -581,9 +625,13 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             rti_domain_destroy(D);
             return fail(RTI_EHIP, "initialising device memory failed: %s", hipGetErrorString(e));
         }
+        if ((rc = upload_tables(D))) {
+            rti_domain_destroy(D);
+            return rc;
+        }
         for (int k = 0; k < dv.nlev; ++k) {
             const LevelPlan &p = plan.lv[k];
-            rc = put_rows_b(D, dv.lv[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
+            rc = put_rows_b(D, D->lvh[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
             if (rc) { rti_domain_destroy(D); return rc; }
             // the lake at rest on the depth as the kernels see it (rounded to FP32 in FP32-bulk)
             rc = device_initial(D, k, nullptr);
@@ -641,7 +689,7 @@ int rti_set_eta(rti_domain *D, int32_t level, const double *eta0)
         std::vector<double> h(n), eta(eta0, eta0 + n);
         for (size_t c = 0; c < n; ++c)
             if (!std::isfinite(eta[c])) return fail(RTI_EINVAL, "eta0 not finite at cell %zu", c);
-        rc = get_rows_b(D, h.data(), p.nx, D->dev.lv[level].h, p.pitch, p.ny);
+        rc = get_rows_b(D, h.data(), p.nx, D->lvh[level].h, p.pitch, p.ny);
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(D->stream));
         return install_initial(D, level, h.data(), eta);
@@ -720,7 +768,7 @@ int rti_max_inundation(rti_domain *D, int32_t level, double *out)
     if (rc) return rc;
     if (!out) return fail(RTI_EINVAL, "out is NULL");
     const LevelPlan &p = D->plan.lv[level];
-    rc = get_rows_b(D, out, p.nx, D->dev.lv[level].zmax, p.pitch, p.ny);
+    rc = get_rows_b(D, out, p.nx, D->lvh[level].zmax, p.pitch, p.ny);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
@@ -731,7 +779,7 @@ int rti_get_state(rti_domain *D, int32_t level, double *eta, double *M, double *
     int rc = check_level(D, level);
     if (rc) return rc;
     const LevelPlan &p = D->plan.lv[level];
-    const LevelDev &L = D->dev.lv[level];
+    const LevelDev &L = D->lvh[level];
     if (eta && (rc = get_rows(D, eta, p.nx, L.eta[D->cur], p.pitch, p.ny))) return rc;
     if (M && (rc = get_rows_b(D, M, p.nx + 1, L.M[D->cur], p.pitch, p.ny))) return rc;
     if (N && (rc = get_rows_b(D, N, p.nx, L.N[D->cur], p.pitch, p.ny + 1))) return rc;
@@ -744,7 +792,7 @@ int rti_set_state(rti_domain *D, int32_t level, const double *eta, const double 
     int rc = check_level(D, level);
     if (rc) return rc;
     const LevelPlan &p = D->plan.lv[level];
-    const LevelDev &L = D->dev.lv[level];
+    const LevelDev &L = D->lvh[level];
     for (int b = 0; b < 2; ++b) {
         if (eta && (rc = put_rows(D, L.eta[b], p.pitch, eta, p.nx, p.ny))) return rc;
         if (M && (rc = put_rows_b(D, L.M[b], p.pitch, M, p.nx + 1, p.ny))) return rc;
@@ -762,7 +810,7 @@ int rti_set_max(rti_domain *D, int32_t level, const double *zmax)
     if (rc) return rc;
     if (!zmax) return fail(RTI_EINVAL, "zmax is NULL");
     const LevelPlan &p = D->plan.lv[level];
-    if ((rc = put_rows_b(D, D->dev.lv[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
+    if ((rc = put_rows_b(D, D->lvh[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
     if ((rc = forget_quiet(D))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
@@ -858,14 +906,27 @@ int rti_active_tiles(rti_domain *D, int64_t *active, int64_t *total, int64_t *ce
     return RTI_OK;
 }
 
+// Sum of the computed-cell slots (synchronises).
+int cells_done(rti_domain *D, unsigned long long *out)
+{
+    std::vector<unsigned long long> part((size_t)(D->plan.ntiles_cap + 255) / 256);
+    HIP_TRY(hipMemcpyAsync(part.data(), D->dev.cells_done, sizeof(unsigned long long) * part.size(),
+                           hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    unsigned long long t = 0;
+    for (auto v : part) t += v;
+    *out = t;
+    return RTI_OK;
+}
+
 int rti_cell_updates(rti_domain *D, int64_t *all, int64_t *computed)
 {
     if (!D || !all || !computed) return fail(RTI_EINVAL, "NULL argument");
     int64_t cells = 0;
     for (const auto &p : D->plan.lv) cells += (int64_t)p.nx * p.ny;
     unsigned long long done = 0;
-    HIP_TRY(hipMemcpyAsync(&done, D->dev.cells_done, sizeof done, hipMemcpyDeviceToHost, D->stream));
-    HIP_TRY(hipStreamSynchronize(D->stream));
+    int rc = cells_done(D, &done);
+    if (rc) return rc;
     *all = cells * D->own_steps;
     *computed = (D->flags & RTI_FLAG_PHASED) ? *all : (int64_t)done;
     return RTI_OK;
@@ -905,20 +966,22 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
     hipEvent_t ev[2] = {nullptr, nullptr};
     const int cur0 = D->cur;
     const int64_t steps0 = D->steps;
-    unsigned long long done0 = 0;           // the trials do not count as computed cells
+    std::vector<unsigned long long> done0((size_t)(D->plan.ntiles_cap + 255) / 256);   // the trials do not count
     int best = D->plan.th;
     double best_ms = 0.0;
     int rc = RTI_OK;
     auto restore = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice, D->stream));
-        HIP_TRY(hipMemcpyAsync(D->dev.cells_done, &done0, sizeof done0, hipMemcpyHostToDevice, D->stream));
+        HIP_TRY(hipMemcpyAsync(D->dev.cells_done, done0.data(), sizeof(unsigned long long) * done0.size(),
+                               hipMemcpyHostToDevice, D->stream));
         D->cur = cur0;
         D->steps = steps0;
         int rc2 = forget_quiet(D);
         return rc2 ? rc2 : reset_counts(D);
     };
     try {
-        HIP_TRY(hipMemcpyAsync(&done0, D->dev.cells_done, sizeof done0, hipMemcpyDeviceToHost, D->stream));
+        HIP_TRY(hipMemcpyAsync(done0.data(), D->dev.cells_done, sizeof(unsigned long long) * done0.size(),
+                               hipMemcpyDeviceToHost, D->stream));
         HIP_TRY(hipStreamSynchronize(D->stream));
         hipError_t e = hipMalloc(&snap, D->plan.level_bytes);
         if (e != hipSuccess) return fail(RTI_ENOMEM, "autotune snapshot of %zu bytes: %s", D->plan.level_bytes, hipGetErrorString(e));
@@ -968,7 +1031,8 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         // leave the domain as it was, whatever failed
         (void)hipStreamSynchronize(D->stream);
         (void)hipMemcpy(D->mem, snap, D->plan.level_bytes, hipMemcpyDeviceToDevice);
-        (void)hipMemcpy(D->dev.cells_done, &done0, sizeof done0, hipMemcpyHostToDevice);
+        (void)hipMemcpy(D->dev.cells_done, done0.data(), sizeof(unsigned long long) * done0.size(),
+                        hipMemcpyHostToDevice);
         D->cur = cur0;
         D->steps = steps0;
         (void)forget_quiet(D);

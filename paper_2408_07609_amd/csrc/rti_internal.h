@@ -6,7 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define RTI_MAX_LEVELS_DEV 16
+#define RTI_MAX_LEVELS_DEV 128
 
 // Tile of the fused kernel: one wavefront of 64 lanes covers 64 columns and
 // writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
@@ -88,16 +88,33 @@ struct DomainDev {
     int32_t s_ntiles;                      // per-phase-kernel tiles over all levels
     int32_t bc[4];
     int32_t bulk32;                        // 1: h, maxima, M, N stored and the momentum computed in FP32
-    int32_t child[RTI_MAX_LEVELS_DEV];     // level indices grouped by parent: lv[p].first_child indexes here
+    int32_t max_ring, max_edge;            // longest child ring (parent cells) and child edge (faces)
     double eps, fc, g;                     // dry threshold, dt/2 g n^2, gravity
     const uint8_t *tinfo;                  // ntiles static bits (TI_*)
     uint8_t *tflag;                        // ntiles: bit0 quiescent after the last step, bit1 after the one before
     int32_t *list;                         // ntiles: active tiles of the current step
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
     const int32_t *tcells;                 // ntiles: cells of the level inside each tile
-    unsigned long long *cells_done;        // cells of all computed tiles, summed over the steps
-    LevelDev lv[RTI_MAX_LEVELS_DEV];
+    unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles, summed over the steps
+    const LevelDev *lv;                    // nlev levels (blocks of a resolution): device table
+    const int32_t *child;                  // level indices grouped by parent: lv[p].first_child indexes here
+    const uint8_t *tlev;                   // ntiles: level of each fused-kernel tile
+    const uint8_t *slev;                   // s_ntiles: level of each per-phase tile
 };
+
+// Reads of the level table and the per-tile level indices go through the
+// constant address space: the table is read-only during a step and the
+// indices used are wavefront-uniform, so these become scalar loads.
+typedef const __attribute__((address_space(4))) LevelDev ConstLevelDev;
+typedef const __attribute__((address_space(4))) int32_t ConstI32;
+typedef const __attribute__((address_space(4))) uint8_t ConstU8;
+__device__ __forceinline__ const LevelDev &level_of(const DomainDev &d, int l)
+{
+    return *(const LevelDev *)&((ConstLevelDev *)d.lv)[l];
+}
+__device__ __forceinline__ int child_level(const DomainDev &d, int k) { return ((ConstI32 *)d.child)[k]; }
+__device__ __forceinline__ int level_of_tile(const DomainDev &d, int g) { return ((ConstU8 *)d.tlev)[g]; }
+__device__ __forceinline__ int level_of_stile(const DomainDev &d, int s) { return ((ConstU8 *)d.slev)[s]; }
 
 // A batch of domains stepped together: member m's tiles are global tiles
 // base[m] .. base[m+1]-1 of one table, and its state buffer at step parity
@@ -110,7 +127,7 @@ struct BatchDev {
     int32_t n, ntiles;
     int32_t *list;                         // ntiles: active global tiles of the current step
     int32_t *count;                        // [flip]
-    unsigned long long *cells_done;        // cells of all computed tiles of all members, summed over the steps
+    unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles of all members
 };
 
 // Parameters of the initial state of one level: the level's origin and

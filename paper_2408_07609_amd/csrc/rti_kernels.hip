@@ -18,14 +18,6 @@
 namespace {
 using namespace rti_dev;
 
-__device__ __forceinline__ int level_of_stile(const DomainDev &d, int blk)
-{
-    int l = 0;
-    #pragma unroll 1
-    for (int k = 1; k < d.nlev; ++k)
-        if (blk >= d.lv[k].s_tile_base) l = k;
-    return l;
-}
 
 struct View {
     const double *h, *eta, *M, *N;
@@ -126,7 +118,7 @@ __device__ double ymom(const View &v, double eps, double r, double gr, double fc
 __global__ __launch_bounds__(256) void k_mass(DomainDev d, int b)
 {
     const int blk = blockIdx.x;
-    const LevelDev &L = d.lv[level_of_stile(d, blk)];
+    const LevelDev &L = level_of(d, level_of_stile(d, blk));
     const int t = blk - L.s_tile_base;
     const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
@@ -146,8 +138,8 @@ __global__ __launch_bounds__(256) void k_mass(DomainDev d, int b)
 __global__ __launch_bounds__(256) void k_jnz(DomainDev d, int b)
 {
     const int c = blockIdx.y + 1;
-    const LevelDev &C = d.lv[c];
-    const LevelDev &Pl = d.lv[C.parent];
+    const LevelDev &C = level_of(d, c);
+    const LevelDev &Pl = level_of(d, C.parent);
     const int fw = C.nx / 3, fh = C.ny / 3;
     const int ring = 2 * fw + 2 * (fh - 2);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,7 +179,7 @@ __global__ __launch_bounds__(256) void k_momentum(DomainDev d, int b)
 {
     const int blk = blockIdx.x;
     const int l = level_of_stile(d, blk);
-    const LevelDev &L = d.lv[l];
+    const LevelDev &L = level_of(d, l);
     const int t = blk - L.s_tile_base;
     const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
@@ -220,8 +212,8 @@ __global__ __launch_bounds__(256) void k_momentum(DomainDev d, int b)
 __global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
 {
     const int c = blockIdx.y + 1;
-    const LevelDev &C = d.lv[c];
-    const LevelDev &Pl = d.lv[C.parent];
+    const LevelDev &C = level_of(d, c);
+    const LevelDev &Pl = level_of(d, C.parent);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int ny = C.ny, nx = C.nx;
     const int I0 = C.off_i, J0 = C.off_j, fw = nx / 3, fh = ny / 3;
@@ -247,7 +239,7 @@ template <typename F>
 __global__ __launch_bounds__(256) void k_finite(DomainDev d, int b, int *flag)
 {
     const int blk = blockIdx.x;
-    const LevelDev &L = d.lv[level_of_stile(d, blk)];
+    const LevelDev &L = level_of(d, level_of_stile(d, blk));
     const int t = blk - L.s_tile_base;
     const int i = (t % L.s_tiles_x) * 64 + (threadIdx.x & 63);
     const int j = (t / L.s_tiles_x) * 4 + (threadIdx.x >> 6);
@@ -262,27 +254,6 @@ __global__ void k_zero_int(int *p, int n)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0;
-}
-
-int max_ring(const DomainDev &d)
-{
-    int m = 0;
-    for (int c = 1; c < d.nlev; ++c) {
-        const int fw = d.lv[c].nx / 3, fh = d.lv[c].ny / 3;
-        const int ring = 2 * fw + 2 * (fh - 2);
-        if (ring > m) m = ring;
-    }
-    return m;
-}
-
-int max_edge(const DomainDev &d)
-{
-    int m = 0;
-    for (int c = 1; c < d.nlev; ++c) {
-        const int e = 2 * d.lv[c].nx + 2 * d.lv[c].ny;
-        if (e > m) m = e;
-    }
-    return m;
 }
 
 // Initial state of one level at t = 0: water level from the depth (and the
@@ -332,7 +303,7 @@ hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s)
 hipError_t launch_jnz(const DomainDev &d, int b, hipStream_t s)
 {
     if (d.nlev < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_jnz, dim3((max_ring(d) + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    hipLaunchKernelGGL(k_jnz, dim3((d.max_ring + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
     return hipGetLastError();
 }
 
@@ -345,7 +316,7 @@ hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s)
 hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s)
 {
     if (d.nlev < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_jnq, dim3((max_edge(d) + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    hipLaunchKernelGGL(k_jnq, dim3((d.max_edge + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct Plan {
     std::vector<LevelPlan> lv;
     std::vector<uint8_t> tinfo;   // static bits per fused-kernel tile (TI_*)
     std::vector<int32_t> tcells;  // cells of the level inside each tile
+    std::vector<uint8_t> tlev;    // level of each fused-kernel tile
+    std::vector<uint8_t> slev;    // level of each per-phase tile
     size_t elem = sizeof(double); // element size of h, maxima, M, N
     size_t level_bytes = 0;       // the level arrays (state, bathymetry, maxima), first in memory
     size_t bytes = 0;
@@ -62,6 +64,11 @@ struct rti_batch;
 struct rti_domain {
     rti_rt::Plan plan;
     DomainDev dev{};
+    std::vector<LevelDev> lvh;           // host copy of the level table (dev.lv points at the device copy)
+    std::vector<int32_t> childh;         // host copy of the child list
+    LevelDev *lv_dev = nullptr;
+    int32_t *child_dev = nullptr;
+    uint8_t *tlev_dev = nullptr, *slev_dev = nullptr;
     hipStream_t stream = nullptr;        // borrowed (the batch's stream while in a batch)
     hipStream_t home_stream = nullptr;   // the stream given at create, restored on leaving a batch
     hipStream_t capture = nullptr;       // private, for graph capture
