@@ -7,6 +7,7 @@ Default workload: the 4-level nest at 810/270/90/30 m (1200x1000, 900^2,
 1500^2, 2400^2 = 10.02 M cells) over a seeded synthetic coast, dt = 0.2 s,
 3 m elliptic uplift, run for the whole 3600 s (18,000 steps) from t = 0,
 inputs resident in HBM.  Prints one JSON line on stdout; progress on stderr.
+--config c3b: C3 split into the 84 blocks of the paper's Table 1;
 --config c4: the batched ensemble (48 uneven scenarios, FP32-bulk, one batch);
 --config c5: forecast serving (Poisson arrivals, continuous batching, p50/p99
 time to forecast).
@@ -305,7 +306,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole configuration)")
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3b", "c4", "c5"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])
     ap.add_argument("--profile-steps", type=int, default=100)
@@ -339,7 +340,7 @@ def main():
     import scenarios
     from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64, Domain
 
-    sc = {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3}[args.config]()
+    sc = {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3, "c3b": scenarios.c3_blocks}[args.config]()
     steps = args.steps if args.steps is not None else sc.steps
     log(f"workload {sc.name}: {len(sc.levels)} levels, {sc.cells} cells, {steps} timed steps")
     d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,

@@ -253,6 +253,87 @@ def c3(scale: int = 1, seed: int = 3) -> Scenario:
 
 
 # ---------------------------------------------------------------------------
+def _block_tree(sc: Scenario, coast, tree):
+    """Append blocks level by level.  tree: one list per finer resolution of
+    (nx, ny, parent block index) entries; the children of each parent are
+    stacked along y with equal gaps (at least 3 parent cells) and centred on
+    the coastline in x at their own mid-height, inside the parent with at
+    least 3 cells of margin."""
+    for blocks in tree:
+        by_parent = {}
+        for (nx, ny, par) in blocks:
+            by_parent.setdefault(par, []).append((nx, ny))
+        for par, kids in by_parent.items():
+            pn = sc.levels[par]
+            pdx = sc.level_dx(par)
+            pox, poy = sc.level_origin(par)
+            total = sum(ny // 3 for _, ny in kids)
+            gap = (pn["ny"] - total) // (len(kids) + 1)
+            assert gap >= 3, f"parent block {par} too short for its children"
+            y = gap
+            for (nx, ny) in kids:
+                fw, fh = nx // 3, ny // 3
+                ymid = poy + (y + fh / 2) * pdx
+                cx = float(coast.xc(np.array([ymid]))[0])
+                off_i = int(round((cx - pox) / pdx - fw / 2))
+                off_i = max(3, min(off_i, pn["nx"] - 3 - fw))
+                sc.levels.append(_level(nx, ny, par, off_i, y))
+                y += fh + gap
+
+
+def c3_blocks(seed: int = 3) -> Scenario:
+    """C3 with the block structure of the paper's Table 1: one root block of
+    1266x1590 at 810 m; 3 blocks at 270 m, 9 at 90 m, 11 at 30 m and 60 at
+    10 m (84 blocks, 47,227,698 cells; the paper: 47,211,444), every block
+    inside one parent block, stacked along the seeded coast of C3."""
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 1266, 1590
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.72 * Lx, Ly, wiggle=5e3,
+                   knots=[(0.0, 0.0), (45e3, 100.0), (90e3, 1000.0), (250e3, 5000.0), (1e9, 5000.0)],
+                   zmax=30.0, slope=1.0 / 1000.0, Lx=Lx, nbumps=6, scale=1)
+    sc = Scenario("c3-blocks84", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=108000)
+    l2 = [(501, 1140, 0), (750, 756, 0), (750, 756, 0)]                         # blocks 1..3
+    l3 = [(186, 1344, 1), (186, 1344, 1), (360, 690, 1)] + [(360, 690, 2)] * 3 + [(360, 690, 3)] * 3   # 4..12
+    l4 = [(450, 1995, 4), (450, 1995, 4), (450, 1995, 5), (450, 1995, 5)] + [(450, 1995, p) for p in range(6, 13)]
+    l5 = []
+    for k, p in enumerate(range(13, 24)):                                       # 11 blocks at 30 m: 13..23
+        l5 += [(540, 969, p)] * (6 if k < 5 else 5)
+    _block_tree(sc, coast, [l2, l3, l4, l5])
+    assert len(sc.levels) == 84
+    _fill_depths(sc, coast)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    sc.source = Source(cx - 150e3, cy, 50e3, 25e3, 0.5 * math.pi, 3.0, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+def small_blocks(seed: int = 21) -> Scenario:
+    """A small multi-block nest for step-level tests: a 90x96 root at 810 m,
+    2 blocks at 270 m, 3 at 90 m (two in one parent) and 2 at 30 m, with a
+    1.5 m uplift across the shoreline."""
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 90, 96
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.6 * Lx, Ly, wiggle=0.03 * Ly,
+                   knots=[(0.0, 0.0), (0.1 * Lx, 20.0), (0.4 * Lx, 200.0), (1e12, 200.0)],
+                   zmax=5.0, slope=5.0 / (0.05 * Lx), Lx=Lx, nbumps=0, scale=1)
+    sc = Scenario("small-blocks", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=0)
+    _block_tree(sc, coast, [[(45, 108, 0), (45, 90, 0)],
+                            [(27, 36, 1), (27, 45, 1), (36, 27, 2)],
+                            [(27, 27, 3), (18, 27, 5)]])
+    _fill_depths(sc, coast)
+    # a near-field uplift across the shoreline, so the finest blocks flood within a few hundred steps
+    cx = float(coast.xc(np.array([Ly / 2]))[0])
+    sc.source = Source(cx - 0.02 * Lx, Ly / 2, 0.08 * Lx, 0.45 * Ly, 0.0, 1.5, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
+# ---------------------------------------------------------------------------
 def _single(seed: int, n: int, amp: float) -> Scenario:
     """One level of n x n cells at 810 m over a C1-style shelf (6000 m deep in
     the west, 50 m of land in the east, 8 shoals), dt = 1 s, with an elliptic

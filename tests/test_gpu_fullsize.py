@@ -46,6 +46,15 @@ def run_random(sc, steps, seed):
     return worst
 
 
+@pytest.mark.timeout(1200)
+def test_c3_blocks_full_size_steps():
+    """The 84-block layout of the paper's Table 1 (3/9/11/60 blocks at
+    270/90/30/10 m, each in its own parent block)."""
+    sc = scenarios.c3_blocks()
+    for k, w in run_random(sc, 2, seed=304).items():
+        assert max(w) <= 1e-9, f"block {k}: {w}"
+
+
 @pytest.mark.timeout(900)
 def test_c2_full_size_steps():
     sc = scenarios.c2()
