@@ -119,7 +119,7 @@ def bench_batch(args):
     import torch
 
     import scenarios
-    from paper_2408_07609_amd import RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64, Batch
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64, Batch
 
     prec = RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64
     scs = scenarios.c4()
@@ -137,7 +137,7 @@ def bench_batch(args):
 
     ds, rows = build(prec, True)
     log(f"autotuned tile rows: {dict(collections.Counter(rows))}")
-    batch = Batch(ds, flags=RTI_FLAG_PERSISTENT if args.persistent else 0)
+    batch = Batch(ds, flags=(RTI_FLAG_PERSISTENT if args.persistent else 0) | (args.flags & RTI_FLAG_NO_ACTIVE))
     batch.step(args.warmup)
     batch.sync()
     stream = batch.stream

@@ -6,16 +6,18 @@
 // edge faces, and the running maxima.  State is read from buffer b and the new
 // state written to buffer b^1, so every tile may recompute its halo.
 //
-// Tile = one wavefront.  Lane L owns column c = x0 - 2 + L and the wavefront
-// streams up the rows of the tile: each iteration loads one row of eta, h, M,
-// N (one coalesced 512-byte access per field), computes the new water level
-// of that row, the face quantities of the row (depth, M^2/D, M N/D ...) and
-// the momentum of the row below, whose up/down neighbours are then in
-// registers; left/right neighbours come from the adjacent lanes through DPP
-// wavefront shifts.  Each face quantity is computed once per tile, so the
-// divisions, square roots and cube roots per cell are those of the formula.
-// The 2 halo lanes on each side and the 3 warm-up rows are recomputed by the
-// neighbouring tiles (the loads hit L2), so HBM sees each array about once.
+// Tile = one wavefront, 60 columns by DomainDev::th rows.  Lane L owns
+// column c = x0 - 2 + L and the wavefront streams up the rows of the tile:
+// iteration t computes the new water level of row t, the face quantities of
+// row t (depth, M^2/D, M N/D ...) and the momentum of row t-1, whose up/down
+// neighbours are then in registers; left/right neighbours come from the
+// adjacent lanes through DPP wavefront shifts.  The raw loads of row t+RTI_PD
+// (one coalesced access per field) are issued in iteration t, so RTI_PD rows
+// of loads are in flight.  Each face quantity is computed once per tile.  The
+// 2 halo lanes on each side and the 3 warm-up rows are recomputed by the
+// neighbouring tiles (most of their loads hit L2).  The tile function serves
+// the single-domain kernels (one workgroup per tile, or a persistent grid)
+// and the batch kernel (tiles of many domains in one launch).
 //
 // Precision: k_fused<double> is the FP64 step.  k_fused<float> is the
 // FP32-bulk step: h, M, N and the maxima are stored in FP32 and the momentum

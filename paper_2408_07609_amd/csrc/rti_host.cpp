@@ -369,7 +369,13 @@ int device_initial(rti_domain *D, int k, const rti_source *src)
         HIP_TRY(hipMemsetAsync(static_cast<char *>(L.M[b]) - in, 0, p.xf_bytes, D->stream));
         HIP_TRY(hipMemsetAsync(static_cast<char *>(L.N[b]) - in, 0, p.yf_bytes, D->stream));
     }
+    // The depth was just uploaded from pageable host memory and the fluxes
+    // cleared; the kernel that reads them and the calls after it wait for
+    // that explicitly instead of relying on the order of the stream (seen to
+    // break when a profiler intercepts the runtime).
+    HIP_TRY(hipStreamSynchronize(D->stream));
     HIP_TRY(launch_init_level(L, D->dev.bulk32, sp, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
     return RTI_OK;
 }
 
@@ -667,6 +673,7 @@ int rti_set_source(rti_domain *D, const rti_source *src)
         }
         int rc = forget_quiet(D);
         if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(D->stream));
         D->steps = 0;
         D->diverged = false;
         return RTI_OK;
@@ -977,7 +984,9 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         D->cur = cur0;
         D->steps = steps0;
         int rc2 = forget_quiet(D);
-        return rc2 ? rc2 : reset_counts(D);
+        if (!rc2) rc2 = reset_counts(D);
+        if (!rc2 && hipStreamSynchronize(D->stream) != hipSuccess) rc2 = fail(RTI_EHIP, "autotune restore failed");
+        return rc2;
     };
     try {
         HIP_TRY(hipMemcpyAsync(done0.data(), D->dev.cells_done, sizeof(unsigned long long) * done0.size(),
