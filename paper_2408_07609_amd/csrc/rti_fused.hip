@@ -28,11 +28,13 @@
 //
 // Active tiles: before each step k_active lists the tiles to compute.  A tile
 // is skipped only when it and its 8 neighbours were quiescent (every cell dry,
-// every face flux zero) after both of the last two steps and it is not pinned
-// (near a level edge or a child's ring/edge).  Such a tile's step is an exact
-// no-op: its cells and faces and all that its stencil reads keep their values,
-// and both state buffers already hold them.  Dry land therefore costs no
-// bandwidth once it is quiet.
+// every face flux zero) after both of the last two steps, and so were its
+// coupled tiles on other levels: near a child's edge, the parent tiles that
+// inject its edge fluxes; near a child's footprint boundary, the child tiles
+// whose blocks its ring means read.  Such a tile's step is an exact no-op: its
+// cells and faces and all that its step reads keep their values, and both
+// state buffers already hold them.  Dry land therefore costs no bandwidth once
+// it is quiet, at nest boundaries too.
 #include <type_traits>
 
 #include "rti_device.h"
@@ -448,11 +450,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 
 // ---------------------------------------------------------------------------
 // Active tiles of the coming step.  A tile is tested with its 9 flag bytes
-// loaded together.
+// loaded together, then, near a nest boundary, the flags of its coupled tiles
+// on the parent or child level (the writers of the injected edge faces it
+// reads, or of the child blocks its ring means read).
 __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_active)
 {
     if (all_active) return 1;
-    if (d.tinfo[g] & TI_PINNED) return 1;
+    const unsigned info = d.tinfo[g];
+    if (info & TI_PINNED) return 1;
     const int l = level_of_tile(d, g);
     const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
@@ -467,6 +472,10 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
             const unsigned f = in ? (unsigned)d.tflag[L.tile_base + tile_index(x, y, L.tiles_x, L.tiles_y)] : 3u;
             acc &= f;
         }
+    }
+    if ((info & TI_DEPS) && (acc & 3u) == 3u) {
+        const int e = d.dep_off[g + 1];
+        for (int k = d.dep_off[g]; k < e; ++k) acc &= (unsigned)d.tflag[d.dep[k]];
     }
     return (acc & 3u) == 3u ? 0 : 1;
 }

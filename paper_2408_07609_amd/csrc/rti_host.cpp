@@ -30,34 +30,81 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-// Static bits of every tile.  A tile's extended region (its cells plus the
-// 2-cell halo its stencil reads, plus one for safety) decides: TI_EDGE when it
-// reaches within 3 cells of the level's outer faces (open sides, injected
-// child edges); TI_CHILD when it reaches within 3 parent cells of a child's
-// footprint boundary (ring cells, edge faces).  Both pin the tile.
-void plan_tiles(Plan &plan, int th)
+// Static bits and coupled tiles of every tile.
+//
+// A tile's extended region (its cells plus the 2-cell halo its stencil reads,
+// plus one for safety) decides: TI_EDGE when it reaches within 3 cells of the
+// level's outer faces (open sides, injected child edges); TI_CHILD when it
+// reaches within 3 parent cells of a child's footprint boundary (ring cells,
+// edge faces).
+//
+// A tile may be skipped only if every input of its step is unchanged over the
+// last two steps.  Its 3x3 neighbourhood covers the inputs on its own level.
+// Two kinds of input come from other levels (the exchanges of Sec. IV-C), and
+// the tiles that write them are listed as its coupled tiles:
+//  - a child tile near the child's edge reads edge faces that the parent
+//    injects: the parent tiles over the tile's read region;
+//  - a parent tile reading the ring means reads the child's 3x3 blocks along
+//    the footprint boundary (cells, their faces, the injected edge faces):
+//    the child tiles within 4 cells of the child's edge under the tile's read
+//    region.
+// The read region is taken 4 cells wider than the tile on every side (2 halo
+// columns and rows, the faces beyond them, one to spare), so the lists hold
+// every writer of those inputs and possibly more.  A tile whose list would
+// pass dep_cap is pinned instead: never skipped, never quiescent.
+void plan_tiles(Plan &plan, int th, size_t dep_cap)
 {
     plan.th = th;
+    const int nlev = (int)plan.lv.size();
     int ntiles = 0;
-    for (auto &p : plan.lv) {
+    std::vector<int> tbase(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        LevelPlan &p = plan.lv[l];
         p.tiles_x = (p.nx + 1 + RTI_TW - 1) / RTI_TW;
         p.tiles_y = (p.ny + 1 + th - 1) / th;
+        tbase[l] = ntiles;
         ntiles += p.tiles_x * p.tiles_y;
     }
     plan.ntiles = ntiles;
     plan.tinfo.assign(ntiles, 0);
     plan.tcells.assign(ntiles, 0);
     plan.tlev.assign(ntiles, 0);
-    const int nlev = (int)plan.lv.size();
-    int base = 0;
+    plan.dep_off.assign((size_t)ntiles + 1, 0);
+    plan.dep.clear();
+    std::vector<int32_t> deps;
+    // tiles of level k over cells [i0, i1] x [j0, j1] (inclusive; face indices nx, ny allowed)
+    auto add_rect = [&](int k, int i0, int i1, int j0, int j1) {
+        const LevelPlan &q = plan.lv[k];
+        i0 = std::max(i0, 0); j0 = std::max(j0, 0);
+        i1 = std::min(i1, q.nx); j1 = std::min(j1, q.ny);
+        if (i0 > i1 || j0 > j1) return;
+        for (int ty = j0 / th; ty <= j1 / th; ++ty)
+            for (int tx = i0 / RTI_TW; tx <= i1 / RTI_TW; ++tx)
+                deps.push_back(tbase[k] + tile_index(tx, ty, q.tiles_x, q.tiles_y));
+    };
     for (int l = 0; l < nlev; ++l) {
         const LevelPlan &p = plan.lv[l];
-        for (int ty = 0; ty < p.tiles_y; ++ty) {
-            for (int tx = 0; tx < p.tiles_x; ++tx) {
+        for (int tl = 0; tl < p.tiles_x * p.tiles_y; ++tl) {   // in tile-number order: lists are appended
+            {
+                const int tx = tile_x(tl, p.tiles_x, p.tiles_y), ty = tile_y(tl, p.tiles_x, p.tiles_y);
                 const int ax = tx * RTI_TW - 3, bx = tx * RTI_TW + RTI_TW + 2;
                 const int ay = ty * th - 3, by = ty * th + th + 2;
+                // read region, cells and faces
+                const int rx0 = tx * RTI_TW - 4, rx1 = tx * RTI_TW + RTI_TW + 3;
+                const int ry0 = ty * th - 4, ry1 = ty * th + th + 3;
                 uint8_t bits = 0;
-                if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) bits |= TI_EDGE | TI_PINNED;
+                deps.clear();
+                if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) {
+                    bits |= TI_EDGE;
+                    if (l > 0) {
+                        // parent cells over the read region (edge faces i = nx map to parent face off_i + nx/3),
+                        // widened by one parent cell
+                        const int i0 = std::max(rx0, 0), i1 = std::min(rx1, p.nx);
+                        const int j0 = std::max(ry0, 0), j1 = std::min(ry1, p.ny);
+                        add_rect(p.parent, p.off_i + i0 / 3 - 1, p.off_i + i1 / 3 + 1, p.off_j + j0 / 3 - 1,
+                                 p.off_j + j1 / 3 + 1);
+                    }
+                }
                 for (int k = l + 1; k < nlev; ++k) {
                     const LevelPlan &C = plan.lv[k];
                     if (C.parent != l) continue;
@@ -65,16 +112,38 @@ void plan_tiles(Plan &plan, int th)
                     const int fy0 = C.off_j, fy1 = C.off_j + C.ny / 3 - 1;
                     const bool meets_outer = ax <= fx1 + 3 && bx >= fx0 - 3 && ay <= fy1 + 3 && by >= fy0 - 3;
                     const bool inside_inner = ax >= fx0 + 3 && bx <= fx1 - 3 && ay >= fy0 + 3 && by <= fy1 - 3;
-                    if (meets_outer && !inside_inner) bits |= TI_CHILD | TI_PINNED;
+                    if (!(meets_outer && !inside_inner)) continue;
+                    bits |= TI_CHILD;
+                    // footprint cells in the read region -> their 3x3 child blocks and the faces above/right
+                    const int a = std::max(rx0, fx0), b = std::min(rx1, fx1);
+                    const int c = std::max(ry0, fy0), e = std::min(ry1, fy1);
+                    if (a > b || c > e) continue;
+                    const int ci0 = 3 * (a - fx0), ci1 = 3 * (b - fx0) + 3;
+                    const int cj0 = 3 * (c - fy0), cj1 = 3 * (e - fy0) + 3;
+                    // only the blocks of ring cells are read: the 4-cell strips along the child's edges
+                    add_rect(k, ci0, std::min(ci1, 3), cj0, cj1);
+                    add_rect(k, std::max(ci0, C.nx - 3), ci1, cj0, cj1);
+                    add_rect(k, ci0, ci1, cj0, std::min(cj1, 3));
+                    add_rect(k, ci0, ci1, std::max(cj0, C.ny - 3), cj1);
                 }
-                const int g = base + tile_index(tx, ty, p.tiles_x, p.tiles_y);
+                const int g = tbase[l] + tl;
+                std::sort(deps.begin(), deps.end());
+                deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+                if (!deps.empty()) {
+                    if (plan.dep.size() + deps.size() <= dep_cap) {
+                        bits |= TI_DEPS;
+                        plan.dep.insert(plan.dep.end(), deps.begin(), deps.end());
+                    } else {
+                        bits |= TI_PINNED;
+                    }
+                }
                 plan.tinfo[g] = bits;
                 plan.tlev[g] = (uint8_t)l;
                 const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
                 plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
+                plan.dep_off[(size_t)g + 1] = (int32_t)plan.dep.size();
             }
         }
-        base += p.tiles_x * p.tiles_y;
     }
 }
 
@@ -189,8 +258,13 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     plan.slev.clear();
     for (int k = 0; k < (int)plan.lv.size(); ++k)
         plan.slev.insert(plan.slev.end(), (size_t)plan.lv[k].s_tiles_x * plan.lv[k].s_tiles_y, (uint8_t)k);
-    plan_tiles(plan, RTI_TH_MIN);             // the most tiles any height gives
+    plan_tiles(plan, RTI_TH_MIN, SIZE_MAX);   // the most tiles any height gives
     const int cap = plan.ntiles;
+    // coupled-tile entries: the larger of the smallest and the default height's (other heights
+    // give about as many or fewer; a tile whose list would not fit is pinned)
+    size_t dep_cap = plan.dep.size();
+    plan_tiles(plan, RTI_TH, SIZE_MAX);
+    dep_cap = std::max(dep_cap, plan.dep.size());
     // tile info, tile flags, active list, tile cells, control block (counts, divergence flag),
     // computed-cell sums (one per active-list workgroup)
     bytes += 2 * align_up((size_t)cap, kAlign) + 2 * align_up((size_t)cap * 4, kAlign) + kAlign
@@ -198,10 +272,12 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     // level table, child list, tile levels, per-phase tile levels
     bytes += align_up(sizeof(LevelDev) * plan.lv.size(), kAlign) + align_up(sizeof(int32_t) * plan.lv.size(), kAlign)
              + align_up((size_t)cap, kAlign) + align_up((size_t)s_ntiles, kAlign);
+    // coupled-tile offsets and lists
+    bytes += align_up(sizeof(int32_t) * ((size_t)cap + 1), kAlign) + align_up(sizeof(int32_t) * std::max<size_t>(dep_cap, 1), kAlign);
     plan.bytes = bytes;
     plan.ntiles_cap = cap;
     plan.s_ntiles = s_ntiles;
-    plan_tiles(plan, RTI_TH);
+    plan.dep_cap = dep_cap;
     return RTI_OK;
 }
 
@@ -244,6 +320,10 @@ int carve(rti_domain *D)
     D->child_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * nl, kAlign)));
     D->tlev_dev = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->slev_dev = reinterpret_cast<uint8_t *>(take(align_up((size_t)D->plan.s_ntiles, kAlign)));
+    D->dep_off_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * (nt + 1), kAlign)));
+    D->dep_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * std::max<size_t>(D->plan.dep_cap, 1), kAlign)));
+    D->dev.dep_off = D->dep_off_dev;
+    D->dev.dep = D->dep_dev;
     D->dev.lv = D->lv_dev;
     D->dev.child = D->child_dev;
     D->dev.tlev = D->tlev_dev;
@@ -437,6 +517,22 @@ int upload_tables(rti_domain *D)
     return RTI_OK;
 }
 
+// The fused kernel's tile tables (static bits, cells, coupled tiles) to the device.
+int upload_tiles(rti_domain *D)
+{
+    const Plan &pl = D->plan;
+    HIP_TRY(hipMemcpyAsync(D->tinfo, pl.tinfo.data(), pl.tinfo.size(), hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipMemcpyAsync(D->tcells, pl.tcells.data(), pl.tcells.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           D->stream));
+    HIP_TRY(hipMemcpyAsync(D->dep_off_dev, pl.dep_off.data(), pl.dep_off.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, D->stream));
+    if (!pl.dep.empty())
+        HIP_TRY(hipMemcpyAsync(D->dep_dev, pl.dep.data(), pl.dep.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));   // the host vectors may change after return
+    return RTI_OK;
+}
+
 void drop_graphs(rti_domain *D)
 {
     for (int p = 0; p < 2; ++p) {
@@ -451,7 +547,7 @@ void drop_graphs(rti_domain *D)
 int retile(rti_domain *D, int th)
 {
     HIP_TRY(hipStreamSynchronize(D->stream));
-    plan_tiles(D->plan, th);
+    plan_tiles(D->plan, th, D->plan.dep_cap);
     DomainDev &dv = D->dev;
     dv.th = th;
     dv.ntiles = D->plan.ntiles;
@@ -464,10 +560,8 @@ int retile(rti_domain *D, int th)
         base += p.tiles_x * p.tiles_y;
     }
     int rc0 = upload_tables(D);
+    if (!rc0) rc0 = upload_tiles(D);
     if (rc0) return rc0;
-    HIP_TRY(hipMemcpyAsync(D->tinfo, D->plan.tinfo.data(), D->plan.tinfo.size(), hipMemcpyHostToDevice, D->stream));
-    HIP_TRY(hipMemcpyAsync(D->tcells, D->plan.tcells.data(), D->plan.tcells.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, D->stream));
     int rc = forget_quiet(D);
     if (!rc) rc = reset_counts(D);
     if (rc) return rc;
@@ -532,6 +626,34 @@ int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes)
         int rc = plan_domain(desc, plan);
         if (rc) return rc;
         *bytes = plan.bytes;
+        return RTI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RTI_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RTI_EINVAL, "unexpected exception");
+    }
+}
+
+// Test hook, not part of the ABI: the fused kernel's tile plan of a
+// descriptor at tile height th (host only; no device is touched).  Called
+// with null arrays it returns the sizes; the arrays then receive ntiles
+// static bits and levels, ntiles + 1 coupled-tile offsets and ndep entries.
+int rti_plan_tiles_for_test(const rti_domain_desc *desc, int th, int32_t *ntiles, int32_t *ndep, uint8_t *tinfo,
+                            uint8_t *tlev, int32_t *dep_off, int32_t *dep)
+{
+    try {
+        if (!ntiles || !ndep) return fail(RTI_EINVAL, "ntiles or ndep is NULL");
+        if (th < RTI_TH_MIN || th > RTI_TH_MAX) return fail(RTI_EINVAL, "tile rows %d outside [%d, %d]", th, RTI_TH_MIN, RTI_TH_MAX);
+        Plan plan;
+        int rc = plan_domain(desc, plan);
+        if (rc) return rc;
+        plan_tiles(plan, th, plan.dep_cap);
+        *ntiles = plan.ntiles;
+        *ndep = (int32_t)plan.dep.size();
+        if (tinfo) std::memcpy(tinfo, plan.tinfo.data(), plan.tinfo.size());
+        if (tlev) std::memcpy(tlev, plan.tlev.data(), plan.tlev.size());
+        if (dep_off) std::memcpy(dep_off, plan.dep_off.data(), plan.dep_off.size() * sizeof(int32_t));
+        if (dep && !plan.dep.empty()) std::memcpy(dep, plan.dep.data(), plan.dep.size() * sizeof(int32_t));
         return RTI_OK;
     } catch (const std::bad_alloc &) {
         return fail(RTI_ENOMEM, "host allocation failed");
@@ -621,17 +743,12 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         }
         carve(D);
         e = hipMemsetAsync(D->mem, 0, plan.bytes, D->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(D->tinfo, plan.tinfo.data(), plan.tinfo.size(), hipMemcpyHostToDevice, D->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(D->tcells, plan.tcells.data(), plan.tcells.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, D->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(D->stream);
         if (e != hipSuccess) {
             rti_domain_destroy(D);
             return fail(RTI_EHIP, "initialising device memory failed: %s", hipGetErrorString(e));
         }
-        if ((rc = upload_tables(D))) {
+        if ((rc = upload_tiles(D)) || (rc = upload_tables(D))) {
             rti_domain_destroy(D);
             return rc;
         }

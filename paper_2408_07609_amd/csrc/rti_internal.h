@@ -54,10 +54,11 @@ __host__ __device__ inline int tile_y(int tl, int tiles_x, int tiles_y)
     return RTI_TILE_ORDER ? tl % tiles_y : tl / tiles_x;
 }
 
-// Static per-tile bits (host-computed at create).
+// Static per-tile bits (host-computed whenever the tile grid is laid out).
 #define TI_PINNED 0x1u      // never skipped and never reported quiescent
 #define TI_CHILD 0x2u       // the tile's extended region meets a child's ring or edge faces
 #define TI_EDGE 0x4u        // the tile's extended region meets the level's outer faces
+#define TI_DEPS 0x8u        // tiles of other levels (DomainDev::dep) must be quiescent too before a skip
 
 // One level on the device.  Every field of a level shares one row pitch P
 // (a multiple of 32 elements, >= nx + 64): cell (i,j), x-face (i,j) and
@@ -100,6 +101,8 @@ struct DomainDev {
     const int32_t *child;                  // level indices grouped by parent: lv[p].first_child indexes here
     const uint8_t *tlev;                   // ntiles: level of each fused-kernel tile
     const uint8_t *slev;                   // s_ntiles: level of each per-phase tile
+    const int32_t *dep_off;                // ntiles + 1: tile g's coupled tiles are dep[dep_off[g] .. dep_off[g+1])
+    const int32_t *dep;                    // tiles of a parent or child level a tile's step reads through the nest
 };
 
 // Reads of the level table and the per-tile level indices go through the

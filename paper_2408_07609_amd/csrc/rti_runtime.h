@@ -42,6 +42,9 @@ struct Plan {
     std::vector<int32_t> tcells;  // cells of the level inside each tile
     std::vector<uint8_t> tlev;    // level of each fused-kernel tile
     std::vector<uint8_t> slev;    // level of each per-phase tile
+    std::vector<int32_t> dep_off; // ntiles + 1 offsets into dep
+    std::vector<int32_t> dep;     // per tile: the tiles of other levels its step reads through the nest
+    size_t dep_cap = 0;           // device entries reserved for dep (a tile whose list does not fit is pinned)
     size_t elem = sizeof(double); // element size of h, maxima, M, N
     size_t level_bytes = 0;       // the level arrays (state, bathymetry, maxima), first in memory
     size_t bytes = 0;
@@ -50,8 +53,9 @@ struct Plan {
     int th = RTI_TH;              // tile rows of the fused kernel
 };
 
-// Tile grid, static tile bits and per-tile cell counts of tile height th.
-void plan_tiles(Plan &plan, int th);
+// Tile grid, static tile bits, per-tile cell counts and coupled tiles of tile
+// height th.  Coupled-tile lists are kept within dep_cap entries in all.
+void plan_tiles(Plan &plan, int th, size_t dep_cap);
 
 // Workgroups of a fused launch over ntiles tiles: one per tile, or a fixed
 // persistent grid of resident wavefronts when that is smaller.
@@ -79,6 +83,7 @@ struct rti_domain {
     int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag
     uint8_t *tinfo = nullptr;
     int32_t *tcells = nullptr;
+    int32_t *dep_off_dev = nullptr, *dep_dev = nullptr;
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;
     int64_t own_steps = 0;               // steps taken by this domain's own launches (not through a batch)

@@ -454,6 +454,46 @@ def small_nested(seed: int = 7, nlev: int = 3, base=(36, 30), child=(27, 27), dx
     return sc
 
 
+def inland_nest(seed: int = 31) -> Scenario:
+    """A nest wholly on dry land, for tests of tile skipping at nest
+    boundaries: a 120x150 root of 90 m cells with a 10 m deep sea south of an
+    east-west coast (row 25) and land 0.3-0.6 m high rising northwards with
+    seeded 0.4 m bumps; a child of 30 m cells (footprint columns 30-89, rows
+    58-87) holding a grandchild of 10 m cells, and a second child beside it
+    (columns 93-113), dt = 0.1 s.  The nest
+    stays dry until water crosses its edges.  `dam` holds, per level, the
+    land cells that start under water (dam_state): a block of water behind
+    the coast (rows 28-49 of the root), south of the child."""
+    rng = np.random.default_rng(seed)
+    dx0 = 90.0
+    nx0, ny0 = 120, 150
+    sc = Scenario("inland-nest", [_level(nx0, ny0), _level(180, 90, 0, 30, 58), _level(180, 90, 1, 60, 15),
+                                  _level(63, 90, 0, 93, 58)], dx0=dx0, dt=0.1, steps=0)
+    Ly = ny0 * dx0
+    yc = 25 * dx0
+    bumps = [(rng.uniform(0, nx0 * dx0), rng.uniform(yc, Ly)) for _ in range(8)]
+    sc.dam = []
+    for k, lv in enumerate(sc.levels):
+        X, Y = sc.cell_centres(k)
+        ground = 0.3 + 0.3 * (Y - yc) / (Ly - yc)
+        for bx, by in bumps:
+            ground = ground + 0.4 * np.exp(-((X - bx) ** 2 + (Y - by) ** 2) / (2.0 * 400.0 ** 2))
+        lv["h"] = np.ascontiguousarray(np.where(Y < yc, 10.0, -ground))
+        sc.dam.append((Y >= 28 * dx0) & (Y < 50 * dx0))
+    sc.check_cfl()
+    return sc
+
+
+def dam_state(sc: Scenario, level: int, level_of_water: float = 5.0):
+    """(eta, M, N) of a level at rest with the cells of sc.dam[level] under
+    the given water level (dry land elsewhere, sea at 0)."""
+    h = sc.levels[level]["h"]
+    eta = np.where(h > 0, 0.0, -h)
+    eta = np.where(sc.dam[level], level_of_water, eta)
+    ny, nx = h.shape
+    return (np.ascontiguousarray(eta), np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx)))
+
+
 def random_state(sc: Scenario, seed: int, flux: float = 5.0):
     """Random (eta, M, N) per level exercising every branch of one step.
 

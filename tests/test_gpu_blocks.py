@@ -68,3 +68,4 @@ def test_blocks_lake_at_rest_and_phased_agree():
     for k in range(len(sc.levels)):
         for x, y in zip(a.get_state(k), b.get_state(k)):
             assert np.array_equal(x, y), f"block {k}: fused and per-phase differ"
+

@@ -1,0 +1,239 @@
+"""The fused kernel's tile plan on the host: static tile bits and the coupled
+tiles that decide when a tile near a nest boundary may be skipped.
+
+A tile is skipped only when every input of its step stayed unchanged over
+the last two steps.  Its 3x3 neighbourhood on its own level covers the
+inputs written on that level; inputs written on another level (the edge
+fluxes a parent injects into a child, the child blocks a parent's ring means
+read, Sec. IV-C) must come from its coupled tiles.  These tests derive, by
+brute force over every cell and face a tile's step reads, the set of tiles
+that write those inputs, and check that the plan's lists hold all of them,
+at several tile heights, on nests with one and several children per level.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import scenarios
+
+TW = 60
+TI_PINNED, TI_CHILD, TI_EDGE, TI_DEPS = 0x1, 0x2, 0x4, 0x8
+
+
+def plan(sc, th):
+    from paper_2408_07609_amd import rti
+    fn = rti.LIB.rti_plan_tiles_for_test
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(rti.rti_domain_desc), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                   ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    desc, keep = rti.make_desc(sc.levels, sc.dx0, sc.dt)
+    nt, nd = ctypes.c_int32(), ctypes.c_int32()
+    assert fn(ctypes.byref(desc), th, ctypes.byref(nt), ctypes.byref(nd), None, None, None, None) == 0
+    tinfo = np.zeros(nt.value, np.uint8)
+    tlev = np.zeros(nt.value, np.uint8)
+    off = np.zeros(nt.value + 1, np.int32)
+    dep = np.zeros(max(nd.value, 1), np.int32)
+    assert fn(ctypes.byref(desc), th, ctypes.byref(nt), ctypes.byref(nd), tinfo.ctypes.data, tlev.ctypes.data,
+              off.ctypes.data, dep.ctypes.data) == 0
+    return tinfo, tlev, off, dep[:nd.value]
+
+
+class Grid:
+    """Tile numbering of the plan: levels in order, row-major tiles of 60
+    columns by th rows; a tile owns the cells and the left / bottom faces of
+    its columns and rows (the last tile column / row also the faces nx, ny)."""
+
+    def __init__(self, sc, th):
+        self.th, self.lv, self.base = th, [], []
+        n = 0
+        for L in sc.levels:
+            ny, nx = L["h"].shape
+            tx, ty = (nx + 1 + TW - 1) // TW, (ny + 1 + th - 1) // th
+            self.lv.append(dict(nx=nx, ny=ny, tx=tx, ty=ty, parent=L["parent"], oi=L["off_i"], oj=L["off_j"]))
+            self.base.append(n)
+            n += tx * ty
+        self.ntiles = n
+
+    def tile(self, k, i, j):
+        L = self.lv[k]
+        assert 0 <= i <= L["nx"] and 0 <= j <= L["ny"], (k, i, j)
+        return self.base[k] + (j // self.th) * L["tx"] + i // TW
+
+    def children(self, l):
+        return [k for k, L in enumerate(self.lv) if L["parent"] == l]
+
+
+def required(G, l, tx, ty):
+    """(own-level writers, other-level writers, reads ring, reads injected
+    faces) of the inputs of tile (tx, ty) of level l, from the fused kernel's
+    access pattern: lanes c = x0-2 .. x0+61, rows t = y0-2 .. min(y0+th, ny)
+    of new water levels (each with the ring mean of its child blocks where it
+    is a ring cell), x-faces of columns up to x0+62 and y-faces of rows up to
+    min(y0+th, ny)+1."""
+    L, th = G.lv[l], G.th
+    nx, ny = L["nx"], L["ny"]
+    x0, y0 = tx * TW, ty * th
+    t1 = min(y0 + th, ny + 1)
+    own, other = set(), set()
+    ring = inj = False
+    cols = range(max(x0 - 2, 0), min(x0 + 61, nx - 1) + 1)
+    rows = range(max(y0 - 2, 0), min(t1, ny - 1) + 1)
+    for i in range(max(x0 - 2, 0), min(x0 + 62, nx) + 1):
+        for j in range(max(y0 - 2, 0), min(t1 + 1, ny) + 1):
+            own.add(G.tile(l, i, j))
+    for k in G.children(l):
+        C = G.lv[k]
+        fw, fh = C["nx"] // 3, C["ny"] // 3
+        for c in cols:
+            I = c - C["oi"]
+            if not 0 <= I < fw:
+                continue
+            for t in rows:
+                J = t - C["oj"]
+                if not 0 <= J < fh or not (I in (0, fw - 1) or J in (0, fh - 1)):
+                    continue
+                ring = True
+                for jj in range(3 * J, 3 * J + 3):
+                    for ii in range(3 * I, 3 * I + 3):
+                        other.add(G.tile(k, ii, jj))                 # eta, h of the child cell
+                        for fi in (ii, ii + 1):                      # its x-faces
+                            if fi in (0, C["nx"]):
+                                own.add(G.tile(l, C["oi"] + fi // 3, C["oj"] + jj // 3))   # injected by this level
+                            else:
+                                other.add(G.tile(k, fi, jj))
+                        for fj in (jj, jj + 1):                      # its y-faces
+                            if fj in (0, C["ny"]):
+                                own.add(G.tile(l, C["oi"] + ii // 3, C["oj"] + fj // 3))
+                            else:
+                                other.add(G.tile(k, ii, fj))
+    if l > 0:
+        p = L["parent"]
+        fw, fh = nx // 3, ny // 3
+        for i in (0, nx):
+            if x0 - 2 <= i <= x0 + 62:
+                for j in range(max(y0 - 2, 0), min(t1, ny - 1) + 1):
+                    inj = True
+                    other.add(G.tile(p, L["oi"] + i // 3, L["oj"] + j // 3))
+        for j in (0, ny):
+            if y0 - 2 <= j <= t1 + 1:
+                for i in range(max(x0 - 2, 0), min(x0 + 61, nx - 1) + 1):
+                    inj = True
+                    other.add(G.tile(p, L["oi"] + i // 3, L["oj"] + j // 3))
+    return own, other, ring, inj
+
+
+def nest_cases():
+    smallest = scenarios.Scenario("smallest-nest", [dict(nx=15, ny=15, parent=-1, off_i=0, off_j=0, h=None),
+                                                    dict(nx=9, ny=9, parent=0, off_i=6, off_j=6, h=None)],
+                                  dx0=810.0, dt=0.2, steps=0)
+    for k in range(2):
+        smallest.levels[k]["h"] = np.ones((smallest.levels[k]["ny"], smallest.levels[k]["nx"]))
+    return {
+        "small_nested3": scenarios.small_nested(seed=7, nlev=3),
+        "wide_child": scenarios.small_nested(seed=11, nlev=2, base=(150, 72), child=(240, 54)),
+        "small_blocks": scenarios.small_blocks(),
+        "inland_nest": scenarios.inland_nest(),
+        "smallest": smallest,
+    }
+
+
+def random_nest(seed):
+    """A random layout obeying the nesting rules: a root of 30-200 by 20-120
+    cells, 1-3 children side by side (3 cells apart, 3 from the parent's
+    edge), sometimes a grandchild; depths do not matter to the plan."""
+    rng = np.random.default_rng(seed)
+    nx0, ny0 = int(rng.integers(30, 201)), int(rng.integers(20, 121))
+    levels = [dict(nx=nx0, ny=ny0, parent=-1, off_i=0, off_j=0)]
+
+    def place(p, n):
+        P = levels[p]
+        x = 3
+        for _ in range(n):
+            fw = int(rng.integers(3, max(4, (P["nx"] - 6) // n)))
+            fh = int(rng.integers(3, P["ny"] - 5))
+            if x + fw > P["nx"] - 3:
+                break
+            oj = int(rng.integers(3, P["ny"] - 3 - fh + 1))
+            levels.append(dict(nx=3 * fw, ny=3 * fh, parent=p, off_i=x, off_j=oj))
+            x += fw + 3 + int(rng.integers(0, 4))
+    place(0, int(rng.integers(1, 4)))
+    if rng.uniform() < 0.6 and levels[1]["nx"] >= 15 and levels[1]["ny"] >= 15:
+        place(1, int(rng.integers(1, 3)))
+    for L in levels:
+        L["h"] = np.ones((L["ny"], L["nx"]))
+    return scenarios.Scenario(f"random-{seed}", levels, dx0=810.0, dt=0.2, steps=0)
+
+
+def aligned_nest(d):
+    """Footprint edges placed at d cells from a tile boundary of the parent
+    (column 60, rows that are multiples of 4 to 7): child A ends at column
+    60 + d and starts at row 12 + d, child B starts at column 64 + d + 3 and
+    ends at row 36 + d; A holds a grandchild whose edges sit at d from A's own
+    tile boundaries."""
+    levels = [dict(nx=150, ny=66, parent=-1, off_i=0, off_j=0)]
+    a0, a1 = 24, 60 + d                       # A: columns a0 .. a1, rows 12 + d .. 40
+    levels.append(dict(nx=3 * (a1 - a0 + 1), ny=3 * (40 - 12 - d + 1), parent=0, off_i=a0, off_j=12 + d))
+    b0 = a1 + 4 + 3
+    levels.append(dict(nx=3 * (140 - b0 + 1), ny=3 * (36 + d - 6 + 1), parent=0, off_i=b0, off_j=6))
+    A = levels[1]
+    g0 = max(3, 20 + d)
+    levels.append(dict(nx=3 * min(60 + d - g0, A["nx"] - 3 - g0), ny=3 * 12, parent=1, off_i=g0, off_j=4 + (d % 4)))
+    for L in levels:
+        L["h"] = np.ones((L["ny"], L["nx"]))
+    return scenarios.Scenario(f"aligned{d:+d}", levels, dx0=810.0, dt=0.2, steps=0)
+
+
+@pytest.mark.parametrize("d", range(-5, 6))
+def test_coupled_tiles_at_tile_boundaries(d):
+    sc = aligned_nest(d)
+    for th in (4, 5, 6, 7):
+        check_plan(sc, th, sc.name)
+
+
+@pytest.mark.parametrize("name", ["small_nested3", "wide_child", "small_blocks", "inland_nest", "smallest"])
+@pytest.mark.parametrize("th", [4, 6, 13, 64])
+def test_coupled_tiles_cover_every_writer(name, th):
+    check_plan(nest_cases()[name], th, name)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_coupled_tiles_random_layouts(seed):
+    sc = random_nest(seed)
+    for th in (4, 5, 7, 9):
+        check_plan(sc, th, sc.name)
+
+
+def check_plan(sc, th, name):
+    tinfo, tlev, off, dep = plan(sc, th)
+    G = Grid(sc, th)
+    assert len(tinfo) == G.ntiles
+    assert not (tinfo & TI_PINNED).any(), "a coupled-tile list did not fit its reservation"
+    assert (np.diff(off) >= 0).all() and off[-1] == len(dep)
+    n_dep_tiles = 0
+    for l, L in enumerate(G.lv):
+        for ty in range(L["ty"]):
+            for tx in range(L["tx"]):
+                g = G.base[l] + ty * L["tx"] + tx
+                assert tlev[g] == l
+                lst = dep[off[g]:off[g + 1]]
+                assert (np.diff(lst) > 0).all() and all(tlev[d] != l for d in lst)
+                assert bool(tinfo[g] & TI_DEPS) == (len(lst) > 0)
+                n_dep_tiles += len(lst) > 0
+                own, other, ring, inj = required(G, l, tx, ty)
+                if ring:
+                    assert tinfo[g] & TI_CHILD, f"tile {g} reads ring means but is not marked"
+                if inj:
+                    assert tinfo[g] & TI_EDGE, f"tile {g} reads injected faces but is not marked"
+                nb = {G.base[l] + y * L["tx"] + x for y in range(ty - 1, ty + 2) for x in range(tx - 1, tx + 2)
+                      if 0 <= x < L["tx"] and 0 <= y < L["ty"]}
+                assert own <= nb, f"tile {g}: own-level inputs outside the 3x3 neighbourhood: {sorted(own - nb)}"
+                missing = other - set(lst.tolist())
+                assert not missing, f"{name} th={th} tile {g} (level {l}, {tx},{ty}): writers {sorted(missing)} not coupled"
+    assert n_dep_tiles > 0
+
+
+def test_root_only_has_no_coupled_tiles():
+    sc = scenarios.small_nested(seed=5, nlev=1, base=(150, 40))
+    tinfo, tlev, off, dep = plan(sc, 6)
+    assert len(dep) == 0 and not (tinfo & (TI_DEPS | TI_PINNED | TI_CHILD)).any()
