@@ -380,7 +380,7 @@ def main():
     dom = max((k for k in prof if k in bpc), key=lambda k: prof[k])
     launch_ms = prof[dom]
     # algorithmic bytes of one launch: the per-cell figure times the cells the
-    # launch computes (skipped quiescent tiles move no data)
+    # launch computes (skipped stationary tiles move no data)
     units = prof_cells if dom == "k_fused" else sc.cells
     alg = bpc[dom] * units
     achieved = alg / (launch_ms * 1e-3) / 1e9

@@ -69,7 +69,7 @@ enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
 
 /* flags of rti_domain_desc */
 #define RTI_FLAG_NO_GRAPH    0x1u   /* rti_step launches kernels one by one instead of replaying a HIP graph */
-#define RTI_FLAG_NO_ACTIVE   0x2u   /* compute every tile; do not skip quiescent dry tiles */
+#define RTI_FLAG_NO_ACTIVE   0x2u   /* compute every tile; do not skip stationary tiles */
 #define RTI_FLAG_PHASED      0x4u   /* one kernel per phase (mass, ring mean, momentum, edge fluxes)
                                        instead of the fused tile kernel; for comparison */
 #define RTI_FLAG_PERSISTENT  0x8u   /* launch the fused kernel with a fixed grid of resident
@@ -184,7 +184,7 @@ int rti_sync(rti_domain *dom);
 int rti_profile(rti_domain *dom, int64_t nsteps, double *ms, const char **names, int32_t cap,
                 int32_t *n_kinds, double *active_cells);
 
-/* Tiles computed in the last step (not skipped as quiescent dry land), all
+/* Tiles computed in the last step (not skipped as stationary), all
  * tiles, and the cells inside the computed tiles.  Before the first step every
  * tile counts as computed.  Synchronises. */
 int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *active_cells);
@@ -192,14 +192,14 @@ int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *
 /* Cell-updates of the steps this domain took through its own launches
  * (rti_step, rti_run, rti_profile; not through a batch): *all counts every
  * cell of every level at every step, *computed only the cells of the tiles
- * the fused kernel computed (quiescent dry tiles skipped).  Synchronises. */
+ * the fused kernel computed (stationary tiles skipped).  Synchronises. */
 int rti_cell_updates(rti_domain *dom, int64_t *all, int64_t *computed);
 
 /* Tile shape of the fused kernel.  A tile is 60 columns wide and `rows` rows
  * high, rows in [RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX] (default
  * RTI_TILE_ROWS_DEFAULT).  The tile shape changes only the work decomposition:
  * results are bitwise the same for every height.  Setting it synchronises,
- * rebuilds the tile tables and forgets the quiescence history (the next two
+ * rebuilds the tile tables and forgets the stationarity history (the next two
  * steps compute every tile). */
 #define RTI_TILE_ROWS_MIN 4
 #define RTI_TILE_ROWS_MAX 64

@@ -27,14 +27,15 @@
 // not accumulate FP32 rounding).
 //
 // Active tiles: before each step k_active lists the tiles to compute.  A tile
-// is skipped only when it and its 8 neighbours were quiescent (every cell dry,
-// every face flux zero) after both of the last two steps, and so were its
+// is stationary after a step that left every value it writes (water levels,
+// fluxes) bitwise unchanged.  A tile is skipped only when it and its 8
+// neighbours were stationary after both of the last two steps, and so were its
 // coupled tiles on other levels: near a child's edge, the parent tiles that
 // inject its edge fluxes; near a child's footprint boundary, the child tiles
-// whose blocks its ring means read.  Such a tile's step is an exact no-op: its
-// cells and faces and all that its step reads keep their values, and both
-// state buffers already hold them.  Dry land therefore costs no bandwidth once
-// it is quiet, at nest boundaries too.
+// whose blocks its ring means read.  Then every value its step reads is what
+// it read in the step before, so its step is an exact no-op, and both state
+// buffers already hold its values (the maxima cannot rise either).  Dry land
+// and water still at rest ahead of the wave therefore cost no bandwidth.
 #include <type_traits>
 
 #include "rti_device.h"
@@ -42,6 +43,10 @@
 
 namespace {
 using namespace rti_dev;
+
+// Bitwise equality (tells -0 from +0), for the stationarity test of a tile.
+__device__ __forceinline__ bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
+__device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_int(a) == __float_as_int(b); }
 
 // Value held by lane+1 (from_right) or lane-1 (from_left): wavefront-wide DPP
 // shifts (wave_shl:1 = 0x130, wave_shr:1 = 0x138); with bound_ctrl set, the
@@ -298,6 +303,8 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
             if (col_cell && row_cell) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
         }
         cur.e1 = e1;
+        // a water level this tile writes (row t is written in the next iteration) left unchanged?
+        if (out_lane && col_cell && t >= y0 && t < y0 + d.th && t < ny) quiet = quiet && same_bits(e1, cur.E);
 
         // Face quantities: x-face c of row t, y-face c at j = t.
         cur.e1L = from_left(e1);
@@ -340,15 +347,16 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
                 if (col_cell && !(rr >= 1 && rr <= ny - 1)) Nnew = (F)nbv;
             }
             if (out_lane) {
-                if (xf_here && (col_xint || root)) *reinterpret_cast<F *>(Mo_a + ofs(rr) * (uint32_t)sizeof(F)) = Mnew;
-                if (col_cell && (yf_int || root)) *reinterpret_cast<F *>(No_a + ofs(rr) * (uint32_t)sizeof(F)) = Nnew;
+                const bool wx = xf_here && (col_xint || root), wy = col_cell && (yf_int || root);
+                if (wx) *reinterpret_cast<F *>(Mo_a + ofs(rr) * (uint32_t)sizeof(F)) = Mnew;
+                if (wy) *reinterpret_cast<F *>(No_a + ofs(rr) * (uint32_t)sizeof(F)) = Nnew;
                 if (col_cell && rr < ny) {
                     *reinterpret_cast<double *>(Eo_a + ofs(rr) * (uint32_t)sizeof(double)) = p.e1;
                     const F v = (F)((p.H > 0.0) ? p.e1 : p.H + p.e1);
                     if (v > p.Z) *reinterpret_cast<F *>(Z_a + ofs(rr) * (uint32_t)sizeof(F)) = v;
-                    quiet = quiet && !(p.H + p.e1 > eps);
                 }
-                quiet = quiet && (Mnew == F(0)) && (Nnew == F(0));
+                // the fluxes this tile writes left unchanged?
+                quiet = quiet && (!wx || same_bits(Mnew, xp.f)) && (!wy || same_bits(Nnew, yp.f));
                 if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew);
             }
         }
@@ -383,7 +391,8 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
 #undef RTI_ROW
     }
 
-    // Quiescence history of the tile: bit1 <- bit0, bit0 <- this step.
+    // Stationarity history of the tile: bit1 <- bit0, bit0 <- this step left
+    // every value the tile writes (water levels, fluxes) bitwise unchanged.
     const bool all_quiet = __all(quiet ? 1 : 0);
     if (lane == 0) {
         const uint8_t old = d.tflag[g];
@@ -474,8 +483,17 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
         }
     }
     if ((info & TI_DEPS) && (acc & 3u) == 3u) {
-        const int e = d.dep_off[g + 1];
-        for (int k = d.dep_off[g]; k < e; ++k) acc &= (unsigned)d.tflag[d.dep[k]];
+        // 8 list entries at a time (the last one repeated past the end), so
+        // the index loads and then the flag loads of a group are in flight
+        // together rather than one after another.
+        const int e = d.dep_off[g + 1] - 1;
+        for (int k = d.dep_off[g]; k <= e; k += 8) {
+            int t[8];
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = d.dep[min(k + u, e)];
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) acc &= (unsigned)d.tflag[t[u]];
+        }
     }
     return (acc & 3u) == 3u ? 0 : 1;
 }

@@ -51,7 +51,7 @@ int fail(int code, const char *fmt, ...)
 // The read region is taken 4 cells wider than the tile on every side (2 halo
 // columns and rows, the faces beyond them, one to spare), so the lists hold
 // every writer of those inputs and possibly more.  A tile whose list would
-// pass dep_cap is pinned instead: never skipped, never quiescent.
+// pass dep_cap is pinned instead: never skipped, never reported stationary.
 void plan_tiles(Plan &plan, int th, size_t dep_cap)
 {
     plan.th = th;
@@ -379,7 +379,7 @@ int check_level(const rti_domain *D, int level)
 
 }  // namespace
 
-// Any host-side change of the state forgets the quiescence history, so the
+// Any host-side change of the state forgets the stationarity history, so the
 // next two steps compute every tile.
 int rti_rt::forget_quiet(rti_domain *D)
 {

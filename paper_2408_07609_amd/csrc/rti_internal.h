@@ -55,10 +55,10 @@ __host__ __device__ inline int tile_y(int tl, int tiles_x, int tiles_y)
 }
 
 // Static per-tile bits (host-computed whenever the tile grid is laid out).
-#define TI_PINNED 0x1u      // never skipped and never reported quiescent
+#define TI_PINNED 0x1u      // never skipped and never reported stationary
 #define TI_CHILD 0x2u       // the tile's extended region meets a child's ring or edge faces
 #define TI_EDGE 0x4u        // the tile's extended region meets the level's outer faces
-#define TI_DEPS 0x8u        // tiles of other levels (DomainDev::dep) must be quiescent too before a skip
+#define TI_DEPS 0x8u        // tiles of other levels (DomainDev::dep) must be stationary too before a skip
 
 // One level on the device.  Every field of a level shares one row pitch P
 // (a multiple of 32 elements, >= nx + 64): cell (i,j), x-face (i,j) and
@@ -92,7 +92,7 @@ struct DomainDev {
     int32_t max_ring, max_edge;            // longest child ring (parent cells) and child edge (faces)
     double eps, fc, g;                     // dry threshold, dt/2 g n^2, gravity
     const uint8_t *tinfo;                  // ntiles static bits (TI_*)
-    uint8_t *tflag;                        // ntiles: bit0 quiescent after the last step, bit1 after the one before
+    uint8_t *tflag;                        // ntiles: bit0 stationary in the last step (nothing it writes changed), bit1 in the one before
     int32_t *list;                         // ntiles: active tiles of the current step
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
     const int32_t *tcells;                 // ntiles: cells of the level inside each tile

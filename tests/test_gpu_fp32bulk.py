@@ -3,7 +3,7 @@ face depth and wet/dry tests in binary64) against the FP64 path.
 
 Stated error after a run (checked, and printed per run): the water level
 differs from FP64 by at most 1e-3 m (RMS 1e-4 m), the maxima by 1e-3 m.
-Still water stays bitwise still, and skipping quiescent tiles is exact in
+Still water stays bitwise still, and skipping stationary tiles is exact in
 this precision too.
 """
 import numpy as np

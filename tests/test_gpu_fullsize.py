@@ -3,7 +3,7 @@ benchmark times (fused kernel, active tiles, HIP graphs).
 
 The oracle computes every cell of a few steps from a seeded random state of
 the full grid (wet/dry mix, both flux signs, every exchange), so every output
-of those steps is compared, not a sample.  Skipping quiescent tiles is checked
+of those steps is compared, not a sample.  Skipping stationary tiles is checked
 to be exact at full size against the same run with skipping off.
 """
 import numpy as np
@@ -72,7 +72,7 @@ def test_c3_full_size_steps():
 @pytest.mark.timeout(900)
 def test_c2_tile_skipping_is_exact():
     """Configuration 2 from its source for 600 steps: the run that skips
-    quiescent dry tiles equals, bit for bit, the run that computes every tile,
+    stationary tiles (dry land, sea still at rest) equals, bit for bit, the run that computes every tile,
     and it did skip tiles."""
     from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE
     sc = scenarios.c2()

@@ -3,7 +3,7 @@
 A tile next to a child's edge, or over a child's footprint boundary, reads
 values that another level writes (the edge fluxes the parent injects; the
 child blocks averaged into the parent's ring cells).  Such a tile is skipped
-only while its coupled tiles on that level are quiescent too.  The nest here
+only while its coupled tiles on that level are stationary too.  The nest here
 lies wholly on dry land, so its edge and ring tiles are skipped until a dam
 break floods across its edges: the skipping run must equal, bit for bit, the
 run that computes every tile, and the oracle.
