@@ -459,7 +459,8 @@ int device_initial(rti_domain *D, int k, const rti_source *src)
     return RTI_OK;
 }
 
-int launch_step(rti_domain *D, int b, hipStream_t s)
+// every_tile: compute every tile this step whatever the domain's flags.
+int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
 {
     if (D->flags & RTI_FLAG_PHASED) {
         HIP_TRY(launch_mass(D->dev, b, s));
@@ -467,7 +468,7 @@ int launch_step(rti_domain *D, int b, hipStream_t s)
         HIP_TRY(launch_momentum(D->dev, b, s));
         HIP_TRY(launch_jnq(D->dev, b, s));
     } else {
-        HIP_TRY(launch_active(D->dev, b, (D->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
+        HIP_TRY(launch_active(D->dev, b, (every_tile || (D->flags & RTI_FLAG_NO_ACTIVE)) ? 1 : 0, s));
         HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s));
     }
     return RTI_OK;
@@ -1119,15 +1120,18 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         for (int c : kCand) {
             if (rc) break;
             if ((rc = retile(D, c)) || (rc = restore())) break;
-            for (int k = 0; k < 2 && !rc; ++k) {      // untimed: the skip history settles
-                rc = launch_step(D, D->cur, D->stream);
+            // Every tile is computed in the trials: the time then measures the
+            // kernel at this height per cell, not how much of the current state
+            // happens to be stationary (early in a run, nearly all of it).
+            for (int k = 0; k < 2 && !rc; ++k) {      // untimed
+                rc = launch_step(D, D->cur, D->stream, true);
                 D->cur ^= 1;
                 D->steps += 1;
             }
             if (rc) break;
             e = hipEventRecord(ev[0], D->stream);
             for (int k = 0; k < nsteps && !rc && e == hipSuccess; ++k) {
-                rc = launch_step(D, D->cur, D->stream);
+                rc = launch_step(D, D->cur, D->stream, true);
                 D->cur ^= 1;
                 D->steps += 1;
             }
