@@ -60,8 +60,12 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
     std::vector<int> tbase(nlev);
     for (int l = 0; l < nlev; ++l) {
         LevelPlan &p = plan.lv[l];
-        p.tiles_x = (p.nx + 1 + RTI_TW - 1) / RTI_TW;
-        p.tiles_y = (p.ny + 1 + th - 1) / th;
+        // A tile writes the cells of its columns and rows and their left and bottom faces.  The
+        // root also writes its last faces (i = nx, j = ny: open sides or walls), so its grid covers
+        // them; a child's last faces are injected by its parent, so its grid covers only its cells.
+        const int fx = (l == 0) ? 1 : 0;
+        p.tiles_x = (p.nx + fx + RTI_TW - 1) / RTI_TW;
+        p.tiles_y = (p.ny + fx + th - 1) / th;
         tbase[l] = ntiles;
         ntiles += p.tiles_x * p.tiles_y;
     }
@@ -78,8 +82,9 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
         i0 = std::max(i0, 0); j0 = std::max(j0, 0);
         i1 = std::min(i1, q.nx); j1 = std::min(j1, q.ny);
         if (i0 > i1 || j0 > j1) return;
-        for (int ty = j0 / th; ty <= j1 / th; ++ty)
-            for (int tx = i0 / RTI_TW; tx <= i1 / RTI_TW; ++tx)
+        // (a child's faces i = nx, j = ny belong to no tile of its own: clip to its last tile)
+        for (int ty = j0 / th; ty <= std::min(j1 / th, q.tiles_y - 1); ++ty)
+            for (int tx = i0 / RTI_TW; tx <= std::min(i1 / RTI_TW, q.tiles_x - 1); ++tx)
                 deps.push_back(tbase[k] + tile_index(tx, ty, q.tiles_x, q.tiles_y));
     };
     for (int l = 0; l < nlev; ++l) {

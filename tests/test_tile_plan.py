@@ -42,22 +42,27 @@ def plan(sc, th):
 class Grid:
     """Tile numbering of the plan: levels in order, row-major tiles of 60
     columns by th rows; a tile owns the cells and the left / bottom faces of
-    its columns and rows (the last tile column / row also the faces nx, ny)."""
+    its columns and rows.  The root's last tile column / row also owns the
+    faces nx, ny (open sides); a child's faces nx, ny are the parent's to
+    write, so its grid covers only its cells."""
 
     def __init__(self, sc, th):
         self.th, self.lv, self.base = th, [], []
         n = 0
-        for L in sc.levels:
+        for k, L in enumerate(sc.levels):
             ny, nx = L["h"].shape
-            tx, ty = (nx + 1 + TW - 1) // TW, (ny + 1 + th - 1) // th
+            f = 1 if k == 0 else 0
+            tx, ty = (nx + f + TW - 1) // TW, (ny + f + th - 1) // th
             self.lv.append(dict(nx=nx, ny=ny, tx=tx, ty=ty, parent=L["parent"], oi=L["off_i"], oj=L["off_j"]))
             self.base.append(n)
             n += tx * ty
         self.ntiles = n
 
     def tile(self, k, i, j):
+        """The tile that writes cell / left face / bottom face (i, j) of level k."""
         L = self.lv[k]
-        assert 0 <= i <= L["nx"] and 0 <= j <= L["ny"], (k, i, j)
+        top = 0 if k > 0 else 1          # a child's faces nx, ny are not its own to write
+        assert 0 <= i <= L["nx"] - 1 + top and 0 <= j <= L["ny"] - 1 + top, (k, i, j)
         return self.base[k] + (j // self.th) * L["tx"] + i // TW
 
     def children(self, l):
@@ -79,8 +84,9 @@ def required(G, l, tx, ty):
     ring = inj = False
     cols = range(max(x0 - 2, 0), min(x0 + 61, nx - 1) + 1)
     rows = range(max(y0 - 2, 0), min(t1, ny - 1) + 1)
-    for i in range(max(x0 - 2, 0), min(x0 + 62, nx) + 1):
-        for j in range(max(y0 - 2, 0), min(t1 + 1, ny) + 1):
+    top = 1 if l == 0 else 0             # a child's faces nx, ny come from the parent (below)
+    for i in range(max(x0 - 2, 0), min(x0 + 62, nx - 1 + top) + 1):
+        for j in range(max(y0 - 2, 0), min(t1 + 1, ny - 1 + top) + 1):
             own.add(G.tile(l, i, j))
     for k in G.children(l):
         C = G.lv[k]
