@@ -99,6 +99,12 @@ int build_tables(rti_batch *B)
     B->tdom.assign(ntiles, 0);
     for (int m = 0; m < n; ++m)
         std::fill(B->tdom.begin() + B->base[m], B->tdom.begin() + B->base[m + 1], (uint16_t)m);
+    // global ring cells: member m's are rbase[m] .. rbase[m+1]-1
+    std::vector<int32_t> rbase(n + 1, 0);
+    for (int m = 0; m < n; ++m) rbase[m + 1] = rbase[m] + B->members[m]->dev.nring;
+    const int nring = rbase[n];
+    std::vector<uint16_t> rdom(std::max(nring, 1), 0);
+    for (int m = 0; m < n; ++m) std::fill(rdom.begin() + rbase[m], rdom.begin() + rbase[m + 1], (uint16_t)m);
     std::vector<DomainDev> doms(n);
     std::vector<uint8_t> par(n);
     B->gen.assign(n, 0);
@@ -109,7 +115,7 @@ int build_tables(rti_batch *B)
         B->gen[m] = B->members[m]->gen;
         B->par[m] = B->members[m]->cur;
     }
-    // layout: doms | base | tdom | par | list | count
+    // layout: doms | base | tdom | par | list | count | cells | rbase | rdom
     const size_t o_doms = 0;
     const size_t o_base = o_doms + align_up(sizeof(DomainDev) * std::max(n, 1), kAlign);
     const size_t o_tdom = o_base + align_up(sizeof(int32_t) * (n + 1), kAlign);
@@ -118,7 +124,9 @@ int build_tables(rti_batch *B)
     const size_t o_count = o_list + align_up(sizeof(int32_t) * std::max(ntiles, 1), kAlign);
     const size_t nslot = (size_t)(std::max(ntiles, 1) + 255) / 256;      // one per active-list workgroup
     const size_t o_cells = o_count + kAlign;
-    const size_t bytes = o_cells + align_up(sizeof(unsigned long long) * nslot, kAlign);
+    const size_t o_rbase = o_cells + align_up(sizeof(unsigned long long) * nslot, kAlign);
+    const size_t o_rdom = o_rbase + align_up(sizeof(int32_t) * (n + 1), kAlign);
+    const size_t bytes = o_rdom + align_up(sizeof(uint16_t) * std::max(nring, 1), kAlign);
     if (bytes > B->mem_bytes) {
         if (B->mem) (void)hipFree(B->mem);
         B->mem = nullptr;
@@ -136,6 +144,9 @@ int build_tables(rti_batch *B)
     HIP_TRY(hipMemsetAsync(p + o_count, 0, 16, B->stream));                  // list counters
     HIP_TRY(hipMemsetAsync(p + o_cells, 0, sizeof(unsigned long long) * nslot, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_cells, &B->cells_done, sizeof B->cells_done, hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipMemcpyAsync(p + o_rbase, rbase.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, B->stream));
+    if (nring)
+        HIP_TRY(hipMemcpyAsync(p + o_rdom, rdom.data(), sizeof(uint16_t) * nring, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));   // host vectors die on return
     BatchDev &bd = B->dev;
     bd.doms = reinterpret_cast<const DomainDev *>(p + o_doms);
@@ -145,6 +156,9 @@ int build_tables(rti_batch *B)
     bd.list = reinterpret_cast<int32_t *>(p + o_list);
     bd.count = reinterpret_cast<int32_t *>(p + o_count);
     bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_cells);
+    bd.rbase = reinterpret_cast<const int32_t *>(p + o_rbase);
+    bd.rdom = reinterpret_cast<const uint16_t *>(p + o_rdom);
+    bd.nring = nring;
     B->nslot = nslot;
     bd.n = n;
     bd.ntiles = ntiles;
@@ -156,7 +170,7 @@ int build_tables(rti_batch *B)
 
 int launch_batch_step(rti_batch *B, int flip, hipStream_t s)
 {
-    HIP_TRY(launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, s));
+    HIP_TRY(launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, B->bulk32, s));
     HIP_TRY(launch_fused_batch(B->dev, flip, B->bulk32,
                                fused_grid(B->dev.ntiles, (B->flags & RTI_FLAG_PERSISTENT) != 0, B->cu_count), s));
     return RTI_OK;
@@ -361,7 +375,8 @@ int rti_batch_profile(rti_batch *B, int64_t nsteps, double *fused_ms, double *ac
         for (int64_t k = 0; k < nsteps && !rc; ++k) {
             const int flip = B->flip;
             hipError_t e = hipEventRecord(ev[0], B->stream);
-            if (e == hipSuccess) e = launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, B->stream);
+            if (e == hipSuccess)
+                e = launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, B->bulk32, B->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[1], B->stream);
             if (e == hipSuccess) e = launch_fused_batch(B->dev, flip, B->bulk32, grid, B->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[2], B->stream);

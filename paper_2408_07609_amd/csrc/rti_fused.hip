@@ -116,6 +116,7 @@ struct RowW {
     double e1;          // new eta of the row
     double e1L, HL;     // new eta and h of the cell on the left
     F MxR, NyL;         // x-face flux on the right, top y-face flux on the left
+    double R;           // ring mean of the row's cell (NaN: not a ring cell, or none wet)
     FaceQ<F> x, y;      // the row's x-face and bottom y-face (j = row)
 };
 
@@ -127,42 +128,84 @@ __device__ __forceinline__ F new_flux(const FaceQ<F> &m, double de, F along, F c
     return momentum_update<F>(m.f, m.cr, m.D, (F)de, along, cross, r, gr, fc);
 }
 
-// New water level of parent cell (c, t) when it lies on the ring of one of
-// the level's children: mean of the wet 3x3 child cells after their own
-// continuity update (computed here from the child's buffer b), summed j outer,
-// i inner; not below the parent's ground; unchanged when none is wet.
+// Child-to-parent mean of ring cell e of the domain (Sec. IV-C): the mean of
+// the wet cells of the child's 3x3 block after their continuity update of this
+// step (computed here from the child's buffer b with the continuity
+// kernel's operations), summed j outer, i inner, not below the parent's
+// ground; NaN when none is wet (the parent cell then keeps its own new
+// level).  Written into the parent's ring array, which the fused kernel of
+// the same step reads.  Only buffer b is read, so this runs before the fused
+// kernel, in the active-list launch.  A mean whose inputs did not change in
+// the last step is left as stored.
 template <typename F>
-__device__ double ring_level(const DomainDev &d, const LevelDev &L, int b, int c, int t, double e1, double hpar)
+__device__ void ring_mean(const DomainDev &d, int b, int e)
 {
-    for (int q = 0; q < L.n_children; ++q) {
-        const LevelDev &C = level_of(d, child_level(d, L.first_child + q));
-        const int I = c - C.off_i, J = t - C.off_j;
-        const int fw = C.nx / 3, fh = C.ny / 3;
-        if (I < 0 || J < 0 || I >= fw || J >= fh) continue;
-        if (!(I == 0 || I == fw - 1 || J == 0 || J == fh - 1)) continue;
-        const int CP = C.pitch;
-        const double *ce = C.eta[b];
-        const F *cm = static_cast<const F *>(C.M[b]), *cn = static_cast<const F *>(C.N[b]);
-        const F *ch = static_cast<const F *>(C.h);
-        double s = 0.0;
-        int nw = 0;
-        for (int jj = 3 * J; jj < 3 * J + 3; ++jj) {
-            for (int ii = 3 * I; ii < 3 * I + 3; ++ii) {
-                const int cc = ii + CP * jj;
-                double ec = ce[cc] - C.r * (((double)cm[cc + 1] - (double)cm[cc]) + ((double)cn[cc + CP] - (double)cn[cc]));
-                const double hc = (double)ch[cc];
-                if (hc + ec < 0.0) ec = -hc;
-                if (hc + ec > d.eps) { s += ec; ++nw; }
-            }
-        }
-        if (nw > 0) {
-            const double v = s / (double)nw;
-            const double ground = -hpar;
-            return (v > ground) ? v : ground;
-        }
-        return e1;
+    const int kp = d.ring_cells[2 * e];                 // child level | parent level << 16
+    const int ij = d.ring_cells[2 * e + 1];
+    const int I = ij & 0xffff, J = ij >> 16;
+    const LevelDev &C = d.lv[kp & 0xffff];
+    const LevelDev &P = d.lv[kp >> 16];                 // loaded together with the child's fields
+    // The block's inputs are the child cells and faces of [3I, 3I+3] x [3J, 3J+3]
+    // (written by at most 2 x 2 child tiles) and the edge faces the parent
+    // injects there (written by the parent tiles of (c, t), (c+1, t), (c, t+1)).
+    // If every one of these tiles left its outputs unchanged in the last step,
+    // the inputs are those of the step the stored mean was computed in (by
+    // induction over the steps since), so the stored mean is this step's too.
+    {
+        const int c = C.off_i + I, t = C.off_j + J, th = d.th;
+        const int ci1 = min(3 * I + 3, C.nx - 1), cj1 = min(3 * J + 3, C.ny - 1);
+        auto flag = [&](const LevelDev &Q, int i, int j) -> unsigned {
+            const int tx = min(i / RTI_TW, Q.tiles_x - 1), ty = min(j / th, Q.tiles_y - 1);
+            return (unsigned)d.tflag[Q.tile_base + tile_index(tx, ty, Q.tiles_x, Q.tiles_y)];
+        };
+        const unsigned acc = flag(C, 3 * I, 3 * J) & flag(C, ci1, 3 * J) & flag(C, 3 * I, cj1) & flag(C, ci1, cj1)
+                           & flag(P, c, t) & flag(P, c + 1, t) & flag(P, c, t + 1) & flag(P, c + 1, t + 1);
+        if (acc & 1u) return;
     }
-    return e1;
+    const int CP = C.pitch;
+    const double *ce = C.eta[b];
+    const F *cm = static_cast<const F *>(C.M[b]), *cn = static_cast<const F *>(C.N[b]);
+    const F *ch = static_cast<const F *>(C.h);
+    const int pc = (C.off_i + I) + P.pitch * (C.off_j + J);
+    const double hpar = (double)static_cast<const F *>(P.h)[pc];
+    // The block's 9 water levels and depths, 12 x-faces and 12 y-faces, all
+    // loaded before any is used (one wait instead of one per cell).
+    const int c0 = 3 * I + CP * (3 * J);
+    double E[9], Hc[9];
+    F Mx[3][4], Ny[4][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            E[3 * r + q] = ce[c0 + CP * r + q];
+            Hc[3 * r + q] = (double)ch[c0 + CP * r + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Mx[r][q] = cm[c0 + CP * r + q];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Ny[r][q] = cn[c0 + CP * r + q];
+    double s = 0.0;
+    int nw = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {          // j outer, i inner
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double ec = E[3 * r + q] - C.r * (((double)Mx[r][q + 1] - (double)Mx[r][q])
+                                              + ((double)Ny[r + 1][q] - (double)Ny[r][q]));
+            const double hc = Hc[3 * r + q];
+            if (hc + ec < 0.0) ec = -hc;
+            if (hc + ec > d.eps) { s += ec; ++nw; }
+        }
+    }
+    // Selected rather than branched, so the parent's depth is loaded with the
+    // block (s / 0 when none is wet is computed and discarded).
+    const double m = s / (double)nw;
+    const double ground = -hpar;
+    const double v = (nw > 0) ? ((m > ground) ? m : ground) : __longlong_as_double(0x7ff8000000000000LL);
+    P.ring[pc] = v;                                     // NaN: none wet
 }
 
 // The new parent flux on a child's edge goes to the 3 child faces it covers.
@@ -246,6 +289,13 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
     };
     auto ld_xf = [&](int row) -> F { return *reinterpret_cast<const F *>(Mb_a + ofs(row) * (uint32_t)sizeof(F)); };
     auto ld_yf = [&](int row) -> F { return *reinterpret_cast<const F *>(Nb_a + ofs(row) * (uint32_t)sizeof(F)); };
+    // Ring means of the step (precomputed in the active-list launch), read like
+    // eta; a tile that meets no child ring reads eta again instead (a cache
+    // hit; the value is not used), so the load needs no branch.
+    const char *Rg_a = reinterpret_cast<const char *>((has_child ? L.ring : Eb) - pad);
+    auto ld_ring = [&](int row) -> double {
+        return *reinterpret_cast<const double *>(Rg_a + ofs(row) * (uint32_t)sizeof(double));
+    };
 
     const int t0 = y0 - 2;
     const int t1 = min(y0 + d.th, ny + 1);     // last iteration; it writes row t1 - 1
@@ -273,6 +323,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
         w[k].H = ld_h(t0 + k);
         w[k].Mx = ld_xf(t0 + k);
         w[k].Ny = ld_yf(t0 + k + 1);
+        w[k].R = ld_ring(t0 + k);
     }
     bool quiet = true;
 
@@ -290,18 +341,17 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
         nxt.H = ld_h(t + RTI_PD);
         nxt.Mx = ld_xf(t + RTI_PD);
         nxt.Ny = ld_yf(t + RTI_PD + 1);
+        nxt.R = ld_ring(t + RTI_PD);
         cur.Z = ld_z(t);
         const bool row_cell = (t >= 0) && (t < ny);
 
-        // Continuity of row t (Eq. 1, FP64), then the child ring overlay.
+        // Continuity of row t (Eq. 1, FP64), then the child-to-parent mean on ring cells.
         const double H_t = cur.H;
         cur.MxR = from_right(cur.Mx);
         double e1 = cur.E - r * (((double)cur.MxR - (double)cur.Mx) + ((double)cur.Ny - (double)p.Ny));
         e1 = (H_t + e1 < 0.0) ? -H_t : e1;
         e1 = (col_cell && row_cell) ? e1 : 0.0;
-        if (has_child) {
-            if (col_cell && row_cell) e1 = ring_level<F>(d, L, b, c, t, e1, H_t);
-        }
+        e1 = (has_child && col_cell && row_cell && cur.R == cur.R) ? cur.R : e1;
         cur.e1 = e1;
         // a water level this tile writes (row t is written in the next iteration) left unchanged?
         if (out_lane && col_cell && t >= y0 && t < y0 + d.th && t < ny) quiet = quiet && same_bits(e1, cur.E);
@@ -469,17 +519,28 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
     if (info & TI_PINNED) return 1;
     const int l = level_of_tile(d, g);
     const LevelDev &L = level_of(d, l);
-    const int tl = g - L.tile_base;
-    const int tx = tile_x(tl, L.tiles_x, L.tiles_y), ty = tile_y(tl, L.tiles_x, L.tiles_y);
+    const int base = L.tile_base, nxt = L.tiles_x, nyt = L.tiles_y;
+    const int tl = g - base;
+    const int tx = tile_x(tl, nxt, nyt), ty = tile_y(tl, nxt, nyt);
+    // The 9 flags are loaded unconditionally (indices clamped into the level,
+    // so all loads are issued together); neighbours outside count as stationary.
+    unsigned f[9];
+    #pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        #pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = min(max(tx + dx, 0), nxt - 1), y = min(max(ty + dy, 0), nyt - 1);
+            f[(dy + 1) * 3 + dx + 1] = d.tflag[base + tile_index(x, y, nxt, nyt)];
+        }
+    }
     unsigned acc = 3u;
     #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
         #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             const int x = tx + dx, y = ty + dy;
-            const bool in = x >= 0 && x < L.tiles_x && y >= 0 && y < L.tiles_y;
-            const unsigned f = in ? (unsigned)d.tflag[L.tile_base + tile_index(x, y, L.tiles_x, L.tiles_y)] : 3u;
-            acc &= f;
+            const bool in = x >= 0 && x < nxt && y >= 0 && y < nyt;
+            acc &= in ? f[(dy + 1) * 3 + dx + 1] : 3u;
         }
     }
     if ((info & TI_DEPS) && (acc & 3u) == 3u) {
@@ -503,7 +564,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
 // step parity b (the list keeps each block's tiles together and in order).
 // The counter of the other parity, read by nobody during this step, is reset
 // for the next one, so no memset is needed between steps.
-__device__ __forceinline__ void append_active(int a, int id, int *count_b, int *count_other, int *list)
+__device__ __forceinline__ void append_active(int a, int id, int tb, int *count_b, int *count_other, int *list)
 {
     __shared__ int wsum[4];
     __shared__ int base;
@@ -523,14 +584,14 @@ __device__ __forceinline__ void append_active(int a, int id, int *count_b, int *
         total += s;
     }
     if (tid == 0) base = total ? atomicAdd(count_b, total) : 0;
-    if (blockIdx.x == 0 && tid == 0) *count_other = 0;
+    if (tb == 0 && tid == 0) *count_other = 0;
     __syncthreads();
     if (a) list[base + before + incl - 1] = id;
 }
 
-// Sum of c over the workgroup added to this workgroup's own slot of part
-// (no atomics: each slot has one writer; the host adds the slots up).
-__device__ __forceinline__ void add_cells(int c, unsigned long long *part)
+// Sum of c over the workgroup added to slot `slot` of part (no atomics: each
+// slot has one writer; the host adds the slots up).
+__device__ __forceinline__ void add_cells(int c, unsigned long long *part, int slot)
 {
     __shared__ int csum[4];
     for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
@@ -538,22 +599,46 @@ __device__ __forceinline__ void add_cells(int c, unsigned long long *part)
     __syncthreads();
     if (threadIdx.x == 0) {
         const int t = (csum[0] + csum[1]) + (csum[2] + csum[3]);
-        if (t) part[blockIdx.x] += (unsigned long long)t;
+        if (t) part[slot] += (unsigned long long)t;
     }
 }
 
-__global__ __launch_bounds__(256) void k_active(DomainDev d, int b, int all_active)
+// The active-list launch: its first nrb workgroups compute the ring means of
+// the step (one thread per ring cell; dispatched first, their gathers are the
+// longest), the others list the active tiles (one thread per tile).  Held to
+// 4 wavefronts per SIMD so that a ring cell's 42 loads can all be in flight.
+template <typename F>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_active(DomainDev d, int b, int all_active,
+                                                                                         int nrb)
 {
-    const int g = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if ((int)blockIdx.x < nrb) {
+        const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
+        if (e < d.nring) ring_mean<F>(d, b, e);
+        return;
+    }
+    const int tb = (int)blockIdx.x - nrb;
+    const int g = tb * 256 + (int)threadIdx.x;
     const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
-    add_cells(a ? d.tcells[g] : 0, d.cells_done);
-    append_active(a, g, &d.count[b], &d.count[b ^ 1], d.list);
+    add_cells(a ? d.tcells[g] : 0, d.cells_done, tb);
+    append_active(a, g, tb, &d.count[b], &d.count[b ^ 1], d.list);
 }
 
-// The same over a batch's global tile table: each member's own flags decide.
-__global__ __launch_bounds__(256) void k_active_batch(BatchDev bd, int flip, int all_active)
+// The same over a batch's global tables: each member's own flags decide, and
+// each ring cell uses its member's state and buffer parity.
+template <typename F>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_active_batch(BatchDev bd, int flip,
+                                                                                               int all_active, int nrb)
 {
-    const int G = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if ((int)blockIdx.x < nrb) {
+        const int E = (int)blockIdx.x * 256 + (int)threadIdx.x;
+        if (E < bd.nring) {
+            const int m = bd.rdom[E];
+            ring_mean<F>(bd.doms[m], bd.par[m] ^ flip, E - bd.rbase[m]);
+        }
+        return;
+    }
+    const int tb = (int)blockIdx.x - nrb;
+    const int G = tb * 256 + (int)threadIdx.x;
     int a = 0, c = 0;
     if (G < bd.ntiles) {
         const int m = bd.tdom[G];
@@ -561,21 +646,29 @@ __global__ __launch_bounds__(256) void k_active_batch(BatchDev bd, int flip, int
         a = tile_active(d, G - bd.base[m], all_active);
         c = a ? d.tcells[G - bd.base[m]] : 0;
     }
-    add_cells(c, bd.cells_done);
-    append_active(a, G, &bd.count[flip], &bd.count[flip ^ 1], bd.list);
+    add_cells(c, bd.cells_done, tb);
+    append_active(a, G, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list);
 }
 
 }  // namespace
 
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_active, dim3((d.ntiles + 255) / 256), dim3(256), 0, s, d, b, all_active);
+    const int nrb = (d.nring + 255) / 256, ntb = (d.ntiles + 255) / 256;
+    if (d.bulk32)
+        hipLaunchKernelGGL(k_active<float>, dim3(nrb + ntb), dim3(256), 0, s, d, b, all_active, nrb);
+    else
+        hipLaunchKernelGGL(k_active<double>, dim3(nrb + ntb), dim3(256), 0, s, d, b, all_active, nrb);
     return hipGetLastError();
 }
 
-hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, hipStream_t s)
+hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_active_batch, dim3((bd.ntiles + 255) / 256), dim3(256), 0, s, bd, flip, all_active);
+    const int nrb = (bd.nring + 255) / 256, ntb = (bd.ntiles + 255) / 256;
+    if (bulk32)
+        hipLaunchKernelGGL(k_active_batch<float>, dim3(nrb + ntb), dim3(256), 0, s, bd, flip, all_active, nrb);
+    else
+        hipLaunchKernelGGL(k_active_batch<double>, dim3(nrb + ntb), dim3(256), 0, s, bd, flip, all_active, nrb);
     return hipGetLastError();
 }
 

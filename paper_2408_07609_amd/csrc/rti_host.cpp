@@ -260,6 +260,26 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         bytes += 2 * p.eta_bytes + 2 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
     }
     plan.level_bytes = bytes;
+    // Ring cells of every child (its footprint's outermost ring of parent cells, Sec. IV-C), and
+    // one ring-mean array, laid out like eta, per level with children.
+    plan.ring.clear();
+    plan.ring_bytes = 0;
+    std::vector<char> has_children(plan.lv.size(), 0);
+    for (int k = 1; k < (int)plan.lv.size(); ++k) {
+        const LevelPlan &C = plan.lv[k];
+        const int fw = C.nx / 3, fh = C.ny / 3;
+        if (fw > 65535 || fh > 32767) return fail(RTI_EINVAL, "level %d: footprint %d x %d too large", k, fw, fh);
+        has_children[C.parent] = 1;
+        for (int J = 0; J < fh; ++J)
+            for (int I = 0; I < fw; ++I)
+                if (I == 0 || I == fw - 1 || J == 0 || J == fh - 1) {
+                    plan.ring.push_back(k | (C.parent << 16));
+                    plan.ring.push_back((J << 16) | I);
+                }
+    }
+    for (int l = 0; l < (int)plan.lv.size(); ++l)
+        if (has_children[l]) plan.ring_bytes += plan.lv[l].eta_bytes;
+    bytes += plan.ring_bytes + align_up(sizeof(int32_t) * std::max<size_t>(plan.ring.size(), 1), kAlign);
     plan.slev.clear();
     for (int k = 0; k < (int)plan.lv.size(); ++k)
         plan.slev.insert(plan.slev.end(), (size_t)plan.lv[k].s_tiles_x * plan.lv[k].s_tiles_y, (uint8_t)k);
@@ -309,6 +329,19 @@ int carve(rti_domain *D)
         L.N[0] = based(pl.yf_bytes, D->plan.elem);
         L.N[1] = based(pl.yf_bytes, D->plan.elem);
     }
+    // ring-mean arrays of the levels with children (after the level arrays: not part of the state)
+    D->ring_mem = p;
+    for (int k = 0; k < (int)D->plan.lv.size(); ++k) D->lvh[k].ring = nullptr;
+    for (int k = 1; k < (int)D->plan.lv.size(); ++k) {
+        const int par = D->plan.lv[k].parent;
+        if (D->lvh[par].ring) continue;
+        const LevelPlan &pl = D->plan.lv[par];
+        const size_t in = (size_t)RTI_PAD_BOTTOM * pl.pitch + 2;
+        D->lvh[par].ring = reinterpret_cast<double *>(take(pl.eta_bytes)) + in;
+    }
+    D->ring_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * std::max<size_t>(D->plan.ring.size(), 1), kAlign)));
+    D->dev.ring_cells = D->ring_dev;
+    D->dev.nring = (int32_t)(D->plan.ring.size() / 2);
     const size_t nt = (size_t)D->plan.ntiles_cap;
     D->tinfo = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.tinfo = D->tinfo;
@@ -757,6 +790,16 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         if ((rc = upload_tiles(D)) || (rc = upload_tables(D))) {
             rti_domain_destroy(D);
             return rc;
+        }
+        // ring-mean arrays: NaN (all bits set) everywhere; each step overwrites the ring cells
+        if (plan.ring_bytes) e = hipMemsetAsync(D->ring_mem, 0xFF, plan.ring_bytes, D->stream);
+        if (e == hipSuccess && !plan.ring.empty())
+            e = hipMemcpyAsync(D->ring_dev, plan.ring.data(), sizeof(int32_t) * plan.ring.size(), hipMemcpyHostToDevice,
+                               D->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(D->stream);
+        if (e != hipSuccess) {
+            rti_domain_destroy(D);
+            return fail(RTI_EHIP, "initialising the ring tables failed: %s", hipGetErrorString(e));
         }
         for (int k = 0; k < dv.nlev; ++k) {
             const LevelPlan &p = plan.lv[k];

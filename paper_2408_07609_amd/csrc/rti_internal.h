@@ -80,6 +80,11 @@ struct LevelDev {
     double r, gr;                          // dt/dx and g*dt/dx
     double *eta[2];
     void *h, *zmax, *M[2], *N[2];          // element type: double, or float when bulk32
+    // Levels with children: per cell, laid out like eta, the child-to-parent
+    // mean of the current step on the cells of the children's rings (written
+    // by the active-list kernel before the fused kernel reads it), NaN on every
+    // other cell and where no child cell of the block is wet.  nullptr otherwise.
+    double *ring;
 };
 
 struct DomainDev {
@@ -103,6 +108,8 @@ struct DomainDev {
     const uint8_t *slev;                   // s_ntiles: level of each per-phase tile
     const int32_t *dep_off;                // ntiles + 1: tile g's coupled tiles are dep[dep_off[g] .. dep_off[g+1])
     const int32_t *dep;                    // tiles of a parent or child level a tile's step reads through the nest
+    int32_t nring;                         // ring cells of all children
+    const int32_t *ring_cells;             // nring x 2: child level | parent level << 16, (J << 16) | I of ring cell (I, J)
 };
 
 // Reads of the level table and the per-tile level indices go through the
@@ -131,6 +138,9 @@ struct BatchDev {
     int32_t *list;                         // ntiles: active global tiles of the current step
     int32_t *count;                        // [flip]
     unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles of all members
+    int32_t nring;                         // ring cells of all members
+    const int32_t *rbase;                  // n + 1: member m's ring cells are global ring cells rbase[m] .. rbase[m+1]-1
+    const uint16_t *rdom;                  // nring: member of each global ring cell
 };
 
 // Parameters of the initial state of one level: the level's origin and
@@ -155,7 +165,8 @@ hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_init_level(const LevelDev &L, int bulk32, const InitSource &sp, hipStream_t s);
+// Also computes the ring means of the step (LevelDev::ring).
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s);
 hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
-hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, hipStream_t s);
+hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s);
 hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s);

@@ -45,6 +45,8 @@ struct Plan {
     std::vector<int32_t> dep_off; // ntiles + 1 offsets into dep
     std::vector<int32_t> dep;     // per tile: the tiles of other levels its step reads through the nest
     size_t dep_cap = 0;           // device entries reserved for dep (a tile whose list does not fit is pinned)
+    std::vector<int32_t> ring;    // 2 per ring cell of every child: child level | parent level << 16, (J << 16) | I
+    size_t ring_bytes = 0;        // the parents' ring-mean arrays (one eta-sized array per level with children)
     size_t elem = sizeof(double); // element size of h, maxima, M, N
     size_t level_bytes = 0;       // the level arrays (state, bathymetry, maxima), first in memory
     size_t bytes = 0;
@@ -84,6 +86,8 @@ struct rti_domain {
     uint8_t *tinfo = nullptr;
     int32_t *tcells = nullptr;
     int32_t *dep_off_dev = nullptr, *dep_dev = nullptr;
+    int32_t *ring_dev = nullptr;         // the ring-cell list (Plan::ring)
+    char *ring_mem = nullptr;            // start of the parents' ring-mean arrays (ring_bytes)
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;
     int64_t own_steps = 0;               // steps taken by this domain's own launches (not through a batch)

@@ -105,8 +105,9 @@ def test_footprint_matches_layout():
     desc, keep = rti.make_desc(sc.levels, sc.dx0, sc.dt)
     b = rti.rti_domain_footprint(desc)
     cells = sc.cells
-    # 8 double arrays of about one cell each (h, maxima, two levels of eta, M and N), padded rows
-    assert 64 * cells <= b <= 64 * cells * 1.6
+    # 8 double arrays of about one cell each (h, maxima, two levels of eta, M and N), padded rows,
+    # plus one more (the ring means) on levels with children
+    assert 64 * cells <= b <= 72 * cells * 1.6
     big = scenarios.c3(scale=1) if os.environ.get("RTI_TEST_BIG") else None
     if big is not None:
         d2, k2 = rti.make_desc(big.levels, big.dx0, big.dt)
