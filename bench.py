@@ -308,6 +308,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3b", "c4", "c5"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
+    ap.add_argument("--tile-rows", type=int, default=0, help="tile height of the fused kernel (0: the library's default)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -347,6 +348,8 @@ def main():
                x0=sc.x0, y0=sc.y0, flags=args.flags, device="cuda:0",
                precision=RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64)
     bpc = BYTES_PER_CELL_FP32_BULK if args.precision == "fp32-bulk" else BYTES_PER_CELL
+    if args.tile_rows:
+        d.set_tile_rows(args.tile_rows)
     d.set_source(*sc.source.astuple())
     init = [d.get_state(k) for k in range(len(sc.levels))]
     zinit = [d.max_inundation(k) for k in range(len(sc.levels))]
@@ -414,6 +417,7 @@ def main():
             "computed_cell_updates": comp1 - comp0,
             "active_cell_updates_per_s": (comp1 - comp0) / wall,
             "flags": args.flags,
+            "tile_rows": d.tile_rows,
         },
         "roofline": {
             "bound": "hbm",

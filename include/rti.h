@@ -203,7 +203,7 @@ int rti_cell_updates(rti_domain *dom, int64_t *all, int64_t *computed);
  * steps compute every tile). */
 #define RTI_TILE_ROWS_MIN 4
 #define RTI_TILE_ROWS_MAX 64
-#define RTI_TILE_ROWS_DEFAULT 6
+#define RTI_TILE_ROWS_DEFAULT 12
 int rti_domain_set_tile_rows(rti_domain *dom, int32_t rows);
 int rti_domain_tile_rows(const rti_domain *dom, int32_t *rows);
 

@@ -11,14 +11,15 @@
 // Tile of the fused kernel: one wavefront of 64 lanes covers 64 columns and
 // writes the middle RTI_TW of them (2 columns of halo on the left, 2 on the
 // right); it streams up DomainDev::th output rows (plus 3 rows of pipeline
-// warm-up).  Short tiles give many wavefronts (the launch drains evenly and
-// many loads are in flight); RTI_TH rows, the default, measured best on
-// gfx950 with RTI_PD = 2.  The height is a per-domain setting between
+// warm-up).  Short tiles give many wavefronts and skip dry or still water
+// finely; tall tiles recompute fewer warm-up rows.  RTI_TH rows, the default,
+// measured best on gfx950 with RTI_PD = 2 over whole runs of the nested
+// workloads (6 to 12 rows within 5 %).  The height is a per-domain setting between
 // RTI_TH_MIN (the 3x3 tile neighbourhood of the skip rule must cover the
 // stencil's reach) and RTI_TH_MAX.
 #define RTI_TW 60
 #ifndef RTI_TH
-#define RTI_TH 6
+#define RTI_TH 12
 #endif
 #define RTI_TH_MIN 4
 #define RTI_TH_MAX 64

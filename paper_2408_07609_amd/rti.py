@@ -23,7 +23,7 @@ RTI_BC_OPEN, RTI_BC_WALL = 0, 1
 RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
 RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED, RTI_FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 RTI_MAX_LEVELS = 128
-RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX, RTI_TILE_ROWS_DEFAULT = 4, 64, 6
+RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX, RTI_TILE_ROWS_DEFAULT = 4, 64, 12
 
 _dptr = ctypes.POINTER(ctypes.c_double)
 

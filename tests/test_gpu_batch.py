@@ -51,10 +51,11 @@ def test_tile_rows_and_persistent_grid_bitwise():
     from paper_2408_07609_amd import RTI_FLAG_NO_GRAPH, RTI_FLAG_PERSISTENT
     sc = scenarios.c2(scale=10)
     ref = make(sc)
-    assert ref.tile_rows == 6
+    from paper_2408_07609_amd.rti import RTI_TILE_ROWS_DEFAULT
+    assert ref.tile_rows == RTI_TILE_ROWS_DEFAULT
     ref.step(130)
     want = snapshot(ref)
-    for rows in (4, 5, 13, 24, 64):
+    for rows in (4, 5, 6, 13, 24, 64):
         d = make(sc, rows=rows)
         assert d.tile_rows == rows
         d.step(130)
