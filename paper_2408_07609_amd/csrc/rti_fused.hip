@@ -1,7 +1,8 @@
 // rti_fused.hip -- the fused time step of the nested long-wave model on
 // gfx950, FP64: one launch computes, for every active tile of every level,
 // the continuity update (paper Eq. 1), the child-to-parent ring mean (Sec.
-// IV-C), the momentum update (Eqs. 2-3) with the wet/dry rule, the root's open
+// IV-C; precomputed for the step in the active-list launch and read here like
+// the water level), the momentum update (Eqs. 2-3) with the wet/dry rule, the root's open
 // or wall sides, the injection of the new parent fluxes into the children's
 // edge faces, and the running maxima.  State is read from buffer b and the new
 // state written to buffer b^1, so every tile may recompute its halo.

@@ -61,7 +61,8 @@ def single(nx, ny, depth, dx=810.0, dt=1.0, **kw):
 @pytest.mark.parametrize("shape", [(3, 3), (3, 41), (41, 3), (61, 7), (121, 13), (7, 121)])
 def test_thin_and_ragged_single_levels(shape):
     """Strips three cells across, and widths and heights one past a tile
-    (60 columns; 6 rows) so the last tile is ragged."""
+    (60 columns; 12 rows, the default height, and 6) so the last tile is
+    ragged."""
     nx, ny = shape
     L = max(nx, ny) * 810.0
     sc = single(nx, ny, lambda X, Y: 200.0 - 190.0 * (X + Y) / (2 * L) + 5.0 * np.sin(X / 3e3))
