@@ -112,3 +112,20 @@ def test_skipping_exact_fp32_bulk_and_batched(precision):
         batch.step(n)
     same(a, b, len(sc.levels), "FP32-bulk skip vs every tile")
     same(c, b, len(sc.levels), "FP32-bulk batched vs every tile")
+
+
+def test_stored_ring_means_match_per_phase_kernels():
+    """The active-list launch keeps a ring cell's stored child-to-parent mean
+    while the tiles writing its inputs stay stationary (here: the nest's
+    rings lie on dry land until the flood crosses them).  The per-phase
+    kernels compute every ring mean afresh each step; the two paths must agree
+    bit for bit through the flood, with and without tile skipping."""
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED
+    sc = scenarios.inland_nest()
+    fused, fused_all, phased = gpu(sc), gpu(sc, flags=RTI_FLAG_NO_ACTIVE), gpu(sc, flags=RTI_FLAG_PHASED)
+    load_dam(sc, fused, fused_all, phased)
+    for n in CHUNKS:
+        for d in (fused, fused_all, phased):
+            d.step(n)
+        same(fused, phased, len(sc.levels), f"fused vs per-phase after {fused.steps} steps")
+        same(fused_all, phased, len(sc.levels), f"fused (every tile) vs per-phase after {fused.steps} steps")
