@@ -210,11 +210,14 @@ __device__ void ring_mean(const DomainDev &d, int b, int e)
 }
 
 // The new parent flux on a child's edge goes to the 3 child faces it covers.
+// cmask: bit q set when child q's edge faces may lie in the tile's output
+// rows and columns (children from the 33rd on are always visited).
 template <typename F>
 __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c, int r, bool xface, bool yface,
-                             F Mnew, F Nnew)
+                             F Mnew, F Nnew, unsigned cmask)
 {
     for (int q = 0; q < L.n_children; ++q) {
+        if (q < 32 && !((cmask >> q) & 1u)) continue;
         const LevelDev &C = level_of(d, child_level(d, L.first_child + q));
         const int fw = C.nx / 3, fh = C.ny / 3;
         const int CP = C.pitch;
@@ -251,6 +254,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
     const uint8_t info = d.tinfo[g];
     const bool has_child = (info & TI_CHILD) != 0;
     const bool root = (l == 0);
+    const unsigned cmask = has_child ? d.tcmask[g] : 0u;   // children whose edges the tile injects
 
     const int lane = (int)threadIdx.x;
     const int c = x0 - 2 + lane;
@@ -408,7 +412,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
                 }
                 // the fluxes this tile writes left unchanged?
                 quiet = quiet && (!wx || same_bits(Mnew, xp.f)) && (!wy || same_bits(Nnew, yp.f));
-                if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew);
+                if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew, cmask);
             }
         }
     };

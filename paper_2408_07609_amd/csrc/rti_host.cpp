@@ -75,6 +75,7 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
     plan.tlev.assign(ntiles, 0);
     plan.dep_off.assign((size_t)ntiles + 1, 0);
     plan.dep.clear();
+    plan.tcmask.assign(ntiles, 0u);
     std::vector<int32_t> deps;
     // tiles of level k over cells [i0, i1] x [j0, j1] (inclusive; face indices nx, ny allowed)
     auto add_rect = [&](int k, int i0, int i1, int j0, int j1) {
@@ -98,6 +99,8 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                 const int rx0 = tx * RTI_TW - 4, rx1 = tx * RTI_TW + RTI_TW + 3;
                 const int ry0 = ty * th - 4, ry1 = ty * th + th + 3;
                 uint8_t bits = 0;
+                uint32_t cmask = 0;
+                int q = 0;   // index of the next child among the level's children (increasing level order)
                 deps.clear();
                 if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) {
                     bits |= TI_EDGE;
@@ -115,6 +118,15 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                     if (C.parent != l) continue;
                     const int fx0 = C.off_i, fx1 = C.off_i + C.nx / 3 - 1;   // footprint, inclusive
                     const int fy0 = C.off_j, fy1 = C.off_j + C.ny / 3 - 1;
+                    {
+                        // output columns x0 .. x0+59, rows y0 .. y0+th-1: does an edge face of child k lie there?
+                        const int ox0 = tx * RTI_TW, ox1 = ox0 + RTI_TW - 1, oy0 = ty * th, oy1 = oy0 + th - 1;
+                        const bool cols = ox0 <= fx1 && ox1 >= fx0, rows = oy0 <= fy1 && oy1 >= fy0;
+                        const bool xcol = (ox0 <= fx0 && fx0 <= ox1) || (ox0 <= fx1 + 1 && fx1 + 1 <= ox1);
+                        const bool yrow = (oy0 <= fy0 && fy0 <= oy1) || (oy0 <= fy1 + 1 && fy1 + 1 <= oy1);
+                        if (q < 32 && ((xcol && rows) || (yrow && cols))) cmask |= 1u << q;
+                        ++q;
+                    }
                     const bool meets_outer = ax <= fx1 + 3 && bx >= fx0 - 3 && ay <= fy1 + 3 && by >= fy0 - 3;
                     const bool inside_inner = ax >= fx0 + 3 && bx <= fx1 - 3 && ay >= fy0 + 3 && by <= fy1 - 3;
                     if (!(meets_outer && !inside_inner)) continue;
@@ -143,6 +155,7 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                     }
                 }
                 plan.tinfo[g] = bits;
+                plan.tcmask[g] = cmask;
                 plan.tlev[g] = (uint8_t)l;
                 const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
                 plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
@@ -297,8 +310,9 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     // level table, child list, tile levels, per-phase tile levels
     bytes += align_up(sizeof(LevelDev) * plan.lv.size(), kAlign) + align_up(sizeof(int32_t) * plan.lv.size(), kAlign)
              + align_up((size_t)cap, kAlign) + align_up((size_t)s_ntiles, kAlign);
-    // coupled-tile offsets and lists
-    bytes += align_up(sizeof(int32_t) * ((size_t)cap + 1), kAlign) + align_up(sizeof(int32_t) * std::max<size_t>(dep_cap, 1), kAlign);
+    // coupled-tile offsets and lists, child masks
+    bytes += align_up(sizeof(int32_t) * ((size_t)cap + 1), kAlign) + align_up(sizeof(int32_t) * std::max<size_t>(dep_cap, 1), kAlign)
+             + align_up(sizeof(uint32_t) * (size_t)cap, kAlign);
     plan.bytes = bytes;
     plan.ntiles_cap = cap;
     plan.s_ntiles = s_ntiles;
@@ -362,6 +376,8 @@ int carve(rti_domain *D)
     D->dep_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * std::max<size_t>(D->plan.dep_cap, 1), kAlign)));
     D->dev.dep_off = D->dep_off_dev;
     D->dev.dep = D->dep_dev;
+    D->tcmask_dev = reinterpret_cast<uint32_t *>(take(align_up(sizeof(uint32_t) * nt, kAlign)));
+    D->dev.tcmask = D->tcmask_dev;
     D->dev.lv = D->lv_dev;
     D->dev.child = D->child_dev;
     D->dev.tlev = D->tlev_dev;
@@ -565,6 +581,8 @@ int upload_tiles(rti_domain *D)
                            D->stream));
     HIP_TRY(hipMemcpyAsync(D->dep_off_dev, pl.dep_off.data(), pl.dep_off.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, D->stream));
+    HIP_TRY(hipMemcpyAsync(D->tcmask_dev, pl.tcmask.data(), pl.tcmask.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           D->stream));
     if (!pl.dep.empty())
         HIP_TRY(hipMemcpyAsync(D->dep_dev, pl.dep.data(), pl.dep.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                D->stream));
@@ -676,9 +694,10 @@ int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes)
 // Test hook, not part of the ABI: the fused kernel's tile plan of a
 // descriptor at tile height th (host only; no device is touched).  Called
 // with null arrays it returns the sizes; the arrays then receive ntiles
-// static bits and levels, ntiles + 1 coupled-tile offsets and ndep entries.
+// static bits, levels and child masks, ntiles + 1 coupled-tile offsets and
+// ndep entries.
 int rti_plan_tiles_for_test(const rti_domain_desc *desc, int th, int32_t *ntiles, int32_t *ndep, uint8_t *tinfo,
-                            uint8_t *tlev, int32_t *dep_off, int32_t *dep)
+                            uint8_t *tlev, int32_t *dep_off, int32_t *dep, uint32_t *tcmask)
 {
     try {
         if (!ntiles || !ndep) return fail(RTI_EINVAL, "ntiles or ndep is NULL");
@@ -693,6 +712,7 @@ int rti_plan_tiles_for_test(const rti_domain_desc *desc, int th, int32_t *ntiles
         if (tlev) std::memcpy(tlev, plan.tlev.data(), plan.tlev.size());
         if (dep_off) std::memcpy(dep_off, plan.dep_off.data(), plan.dep_off.size() * sizeof(int32_t));
         if (dep && !plan.dep.empty()) std::memcpy(dep, plan.dep.data(), plan.dep.size() * sizeof(int32_t));
+        if (tcmask) std::memcpy(tcmask, plan.tcmask.data(), plan.tcmask.size() * sizeof(uint32_t));
         return RTI_OK;
     } catch (const std::bad_alloc &) {
         return fail(RTI_ENOMEM, "host allocation failed");

@@ -109,6 +109,7 @@ struct DomainDev {
     const uint8_t *slev;                   // s_ntiles: level of each per-phase tile
     const int32_t *dep_off;                // ntiles + 1: tile g's coupled tiles are dep[dep_off[g] .. dep_off[g+1])
     const int32_t *dep;                    // tiles of a parent or child level a tile's step reads through the nest
+    const uint32_t *tcmask;                // ntiles: bit q = child q of the tile's level has edge faces in its output
     int32_t nring;                         // ring cells of all children
     const int32_t *ring_cells;             // nring x 2: child level | parent level << 16, (J << 16) | I of ring cell (I, J)
 };

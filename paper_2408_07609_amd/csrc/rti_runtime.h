@@ -44,6 +44,8 @@ struct Plan {
     std::vector<uint8_t> slev;    // level of each per-phase tile
     std::vector<int32_t> dep_off; // ntiles + 1 offsets into dep
     std::vector<int32_t> dep;     // per tile: the tiles of other levels its step reads through the nest
+    std::vector<uint32_t> tcmask; // per tile: children (bit = index among the level's children, first 32)
+                                  // whose edge faces lie in the tile's output rows and columns
     size_t dep_cap = 0;           // device entries reserved for dep (a tile whose list does not fit is pinned)
     std::vector<int32_t> ring;    // 2 per ring cell of every child: child level | parent level << 16, (J << 16) | I
     size_t ring_bytes = 0;        // the parents' ring-mean arrays (one eta-sized array per level with children)
@@ -86,6 +88,7 @@ struct rti_domain {
     uint8_t *tinfo = nullptr;
     int32_t *tcells = nullptr;
     int32_t *dep_off_dev = nullptr, *dep_dev = nullptr;
+    uint32_t *tcmask_dev = nullptr;
     int32_t *ring_dev = nullptr;         // the ring-cell list (Plan::ring)
     char *ring_mem = nullptr;            // start of the parents' ring-mean arrays (ring_bytes)
     int cur = 0;                         // buffer holding the current state

@@ -26,16 +26,19 @@ def plan(sc, th):
     fn = rti.LIB.rti_plan_tiles_for_test
     fn.restype = ctypes.c_int
     fn.argtypes = [ctypes.POINTER(rti.rti_domain_desc), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
-                   ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                   ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p]
     desc, keep = rti.make_desc(sc.levels, sc.dx0, sc.dt)
     nt, nd = ctypes.c_int32(), ctypes.c_int32()
-    assert fn(ctypes.byref(desc), th, ctypes.byref(nt), ctypes.byref(nd), None, None, None, None) == 0
+    assert fn(ctypes.byref(desc), th, ctypes.byref(nt), ctypes.byref(nd), None, None, None, None, None) == 0
     tinfo = np.zeros(nt.value, np.uint8)
     tlev = np.zeros(nt.value, np.uint8)
     off = np.zeros(nt.value + 1, np.int32)
     dep = np.zeros(max(nd.value, 1), np.int32)
+    cmask = np.zeros(nt.value, np.uint32)
     assert fn(ctypes.byref(desc), th, ctypes.byref(nt), ctypes.byref(nd), tinfo.ctypes.data, tlev.ctypes.data,
-              off.ctypes.data, dep.ctypes.data) == 0
+              off.ctypes.data, dep.ctypes.data, cmask.ctypes.data) == 0
+    plan.cmask = cmask
     return tinfo, tlev, off, dep[:nd.value]
 
 
@@ -234,6 +237,17 @@ def check_plan(sc, th, name):
                 nb = {G.base[l] + y * L["tx"] + x for y in range(ty - 1, ty + 2) for x in range(tx - 1, tx + 2)
                       if 0 <= x < L["tx"] and 0 <= y < L["ty"]}
                 assert own <= nb, f"tile {g}: own-level inputs outside the 3x3 neighbourhood: {sorted(own - nb)}"
+                if tinfo[g] & TI_CHILD:
+                    # the child mask holds every child whose edge faces lie in the tile's output
+                    for q, k in enumerate(G.children(l)[:32]):
+                        C = G.lv[k]
+                        fw, fh = C["nx"] // 3, C["ny"] // 3
+                        ox = range(tx * TW, tx * TW + TW)
+                        oy = range(ty * th, ty * th + th)
+                        hit = any(c in ox for c in (C["oi"], C["oi"] + fw)) and any(C["oj"] <= r < C["oj"] + fh for r in oy) \
+                            or any(r in oy for r in (C["oj"], C["oj"] + fh)) and any(C["oi"] <= c < C["oi"] + fw for c in ox)
+                        if hit:
+                            assert plan.cmask[g] >> q & 1, f"tile {g}: child {k} injects here but is not in the mask"
                 missing = other - set(lst.tolist())
                 assert not missing, f"{name} th={th} tile {g} (level {l}, {tx},{ty}): writers {sorted(missing)} not coupled"
     assert n_dep_tiles > 0
