@@ -69,3 +69,45 @@ def test_blocks_lake_at_rest_and_phased_agree():
         for x, y in zip(a.get_state(k), b.get_state(k)):
             assert np.array_equal(x, y), f"block {k}: fused and per-phase differ"
 
+
+
+def many_children(nchild=34):
+    """A 230x24 root (land in the west, sea in the east) holding nchild
+    children of 9x9 cells in a row, 3 parent cells apart: more children than
+    the per-tile child masks describe (32); the wave starts near the last
+    children."""
+    levels = [dict(nx=230, ny=24, parent=-1, off_i=0, off_j=0, h=None)]
+    for q in range(nchild):
+        levels.append(dict(nx=9, ny=9, parent=0, off_i=3 + 6 * q, off_j=10, h=None))
+    sc = scenarios.Scenario(f"children{nchild}", levels, dx0=810.0, dt=0.5, steps=0)
+    for k in range(len(levels)):
+        X, Y = sc.cell_centres(k)
+        sc.levels[k]["h"] = np.ascontiguousarray(-20.0 + 60.0 * X / (230 * 810.0) + 3.0 * np.sin(Y / 2e3))
+    sc.source = scenarios.Source(0.85 * 230 * 810.0, 12 * 810.0, 20e3, 6e3, 0.0, 2.0, scenarios.GAUSS)
+    sc.check_cfl()
+    return sc
+
+
+def test_more_than_32_children():
+    """Ring means and edge injection for children beyond the 32 a tile's
+    child mask holds: one step from a random state against the oracle, and a
+    source run bitwise against the per-phase kernels."""
+    from paper_2408_07609_amd import RTI_FLAG_PHASED
+    sc = many_children()
+    d, o = gpu(sc), oracle.OracleDomain(**sc.oracle_kwargs())
+    for k, (e, M, N) in enumerate(scenarios.random_state(sc, 12, flux=3.0)):
+        h = sc.levels[k]["h"]
+        z = np.where(h > 0, e, h + e)
+        d.set_state(k, e, M, N)
+        d.set_max(k, z)
+        o.set_state(k, eta=e, M=M, N=N, zmax=z)
+    d.step(1)
+    o.step(1)
+    compare(d, o, len(sc.levels), 1e-12, "one step")
+    a, b = gpu(sc), gpu(sc, flags=RTI_FLAG_PHASED)
+    for x in (a, b):
+        x.set_source(*sc.source.astuple())
+        x.step(400)
+    for k in range(len(sc.levels)):
+        for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
+            assert np.array_equal(x, y), f"level {k}: fused and per-phase differ"

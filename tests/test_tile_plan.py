@@ -200,6 +200,13 @@ def test_coupled_tiles_at_tile_boundaries(d):
         check_plan(sc, th, sc.name)
 
 
+def test_coupled_tiles_with_more_than_32_children():
+    from test_gpu_blocks import many_children
+    sc = many_children()
+    for th in (4, 6, 12):
+        check_plan(sc, th, sc.name)
+
+
 @pytest.mark.parametrize("name", ["small_nested3", "wide_child", "small_blocks", "inland_nest", "smallest"])
 @pytest.mark.parametrize("th", [4, 6, 13, 64])
 def test_coupled_tiles_cover_every_writer(name, th):
