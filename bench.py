@@ -119,7 +119,8 @@ def bench_batch(args):
     import torch
 
     import scenarios
-    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64, Batch
+    from paper_2408_07609_amd import (RTI_FLAG_NO_ACTIVE, RTI_FLAG_NO_GRAPH, RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64,
+                                      Batch)
 
     prec = RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64
     scs = scenarios.c4()
@@ -127,8 +128,11 @@ def bench_batch(args):
     steps = args.steps if args.steps is not None else 2000
     log(f"c4: {len(scs)} members, {cells} cells, {steps} timed steps, {args.precision}")
 
+    # the members get the same skipping and graph choices as the batch, for the one-after-another comparison
+    member_flags = args.flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_NO_GRAPH)
+
     def build(precision, tune):
-        ds = [make_domain(sc, precision) for sc in scs]
+        ds = [make_domain(sc, precision, member_flags) for sc in scs]
         rows = []
         if tune:
             for d in ds:
@@ -137,7 +141,8 @@ def bench_batch(args):
 
     ds, rows = build(prec, True)
     log(f"autotuned tile rows: {dict(collections.Counter(rows))}")
-    batch = Batch(ds, flags=(RTI_FLAG_PERSISTENT if args.persistent else 0) | (args.flags & RTI_FLAG_NO_ACTIVE))
+    batch = Batch(ds, flags=(RTI_FLAG_PERSISTENT if args.persistent else 0)
+                  | (args.flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_NO_GRAPH)))
     batch.step(args.warmup)
     batch.sync()
     stream = batch.stream

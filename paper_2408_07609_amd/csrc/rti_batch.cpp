@@ -386,6 +386,7 @@ int rti_batch_profile(rti_batch *B, int64_t nsteps, double *fused_ms, double *ac
             if (e == hipSuccess) e = hipEventElapsedTime(&tf, ev[1], ev[2]);
             int cnt = 0;
             if (e == hipSuccess) e = hipMemcpy(&cnt, B->dev.count + flip, sizeof(int), hipMemcpyDeviceToHost);
+            cnt = std::min(cnt, B->dev.ntiles);        // the list holds at most one entry per tile
             if (e == hipSuccess && cnt > 0) {
                 list.resize(cnt);
                 e = hipMemcpy(list.data(), B->dev.list, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost);

@@ -474,7 +474,7 @@ __device__ __forceinline__ int slice_pos(int n_active, int slot)
 template <typename F>
 __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
 {
-    const int pos = slice_pos(d.count[b], (int)(blockIdx.x >> 3));
+    const int pos = slice_pos(min(d.count[b], d.ntiles), (int)(blockIdx.x >> 3));
     if (pos >= 0) fused_tile<F>(d, b, d.list[pos]);
 }
 
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
 template <typename F>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_loop(DomainDev d, int b)
 {
-    const int n_active = d.count[b];
+    const int n_active = min(d.count[b], d.ntiles);
     for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
         const int pos = slice_pos(n_active, slot);
         if (pos < 0) break;
@@ -502,7 +502,7 @@ template <typename F>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_batch(BatchDev bd, int flip)
 {
     ConstDomainDev *doms = (ConstDomainDev *)bd.doms;
-    const int n_active = bd.count[flip];
+    const int n_active = min(bd.count[flip], bd.ntiles);
     for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
         const int pos = slice_pos(n_active, slot);
         if (pos < 0) break;
@@ -569,7 +569,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
 // step parity b (the list keeps each block's tiles together and in order).
 // The counter of the other parity, read by nobody during this step, is reset
 // for the next one, so no memset is needed between steps.
-__device__ __forceinline__ void append_active(int a, int id, int tb, int *count_b, int *count_other, int *list)
+__device__ __forceinline__ void append_active(int a, int id, int tb, int *count_b, int *count_other, int *list, int cap)
 {
     __shared__ int wsum[4];
     __shared__ int base;
@@ -591,7 +591,12 @@ __device__ __forceinline__ void append_active(int a, int id, int tb, int *count_
     if (tid == 0) base = total ? atomicAdd(count_b, total) : 0;
     if (tb == 0 && tid == 0) *count_other = 0;
     __syncthreads();
-    if (a) list[base + before + incl - 1] = id;
+    // A list holds at most cap (= tiles) entries; the bound also keeps the
+    // writes inside the list if the launch were ever executed twice for one
+    // step (the count would then pass cap; the first cap entries, which
+    // include every active tile, are what the fused kernel reads).
+    const int pos = base + before + incl - 1;
+    if (a && pos < cap) list[pos] = id;
 }
 
 // Sum of c over the workgroup added to slot `slot` of part (no atomics: each
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int g = tb * 256 + (int)threadIdx.x;
     const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
     add_cells(a ? d.tcells[g] : 0, d.cells_done, tb);
-    append_active(a, g, tb, &d.count[b], &d.count[b ^ 1], d.list);
+    append_active(a, g, tb, &d.count[b], &d.count[b ^ 1], d.list, d.ntiles);
 }
 
 // The same over a batch's global tables: each member's own flags decide, and
@@ -652,7 +657,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         c = a ? d.tcells[G - bd.base[m]] : 0;
     }
     add_cells(c, bd.cells_done, tb);
-    append_active(a, G, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list);
+    append_active(a, G, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list, bd.ntiles);
 }
 
 }  // namespace

@@ -544,6 +544,7 @@ int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
     HIP_TRY(hipStreamSynchronize(D->stream));
     const bool fresh = D->steps == D->tiles_step;   // no step since the tile tables were built
     if (fresh) n = D->dev.ntiles;
+    n = std::min(std::max(n, 0), D->dev.ntiles);   // the list holds at most one entry per tile
     std::vector<int32_t> list(n);
     if (!fresh && n > 0) {
         HIP_TRY(hipMemcpyAsync(list.data(), D->dev.list, sizeof(int32_t) * n, hipMemcpyDeviceToHost, D->stream));
