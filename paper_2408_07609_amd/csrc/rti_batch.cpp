@@ -115,13 +115,14 @@ int build_tables(rti_batch *B)
         B->gen[m] = B->members[m]->gen;
         B->par[m] = B->members[m]->cur;
     }
-    // layout: doms | base | tdom | par | list | count | cells | rbase | rdom
+    // layout: doms | base | tdom | par | list | lmeta | count | cells | rbase | rdom
     const size_t o_doms = 0;
     const size_t o_base = o_doms + align_up(sizeof(DomainDev) * std::max(n, 1), kAlign);
     const size_t o_tdom = o_base + align_up(sizeof(int32_t) * (n + 1), kAlign);
     const size_t o_par = o_tdom + align_up(sizeof(uint16_t) * std::max(ntiles, 1), kAlign);
     const size_t o_list = o_par + align_up((size_t)std::max(n, 1), kAlign);
-    const size_t o_count = o_list + align_up(sizeof(int32_t) * std::max(ntiles, 1), kAlign);
+    const size_t o_lmeta = o_list + align_up(sizeof(int32_t) * std::max(ntiles, 1), kAlign);
+    const size_t o_count = o_lmeta + align_up(sizeof(int32_t) * std::max(ntiles, 1), kAlign);
     const size_t nslot = (size_t)(std::max(ntiles, 1) + 255) / 256;      // one per active-list workgroup
     const size_t o_cells = o_count + kAlign;
     const size_t o_rbase = o_cells + align_up(sizeof(unsigned long long) * nslot, kAlign);
@@ -154,6 +155,7 @@ int build_tables(rti_batch *B)
     bd.tdom = reinterpret_cast<const uint16_t *>(p + o_tdom);
     bd.par = reinterpret_cast<const uint8_t *>(p + o_par);
     bd.list = reinterpret_cast<int32_t *>(p + o_list);
+    bd.lmeta = reinterpret_cast<int32_t *>(p + o_lmeta);
     bd.count = reinterpret_cast<int32_t *>(p + o_count);
     bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_cells);
     bd.rbase = reinterpret_cast<const int32_t *>(p + o_rbase);

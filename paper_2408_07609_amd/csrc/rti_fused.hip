@@ -244,9 +244,8 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
 // One tile g of domain d: read buffer b, write buffer b^1 (paper Eqs. 1-3
 // and the nest exchanges of Sec. IV-C for the tile's cells and faces).
 template <typename F>
-__device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g)
+__device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int l)
 {
-    const int l = level_of_tile(d, g);
     const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
     const int x0 = tile_x(tl, L.tiles_x, L.tiles_y) * RTI_TW;
@@ -475,7 +474,7 @@ template <typename F>
 __global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
 {
     const int pos = slice_pos(min(d.count[b], d.ntiles), (int)(blockIdx.x >> 3));
-    if (pos >= 0) fused_tile<F>(d, b, d.list[pos]);
+    if (pos >= 0) fused_tile<F>(d, b, d.list[pos], d.lmeta[pos]);
 }
 
 // A persistent grid: every workgroup loops over tiles.  (The loop costs the
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
         const int pos = slice_pos(n_active, slot);
         if (pos < 0) break;
-        fused_tile<F>(d, b, d.list[pos]);
+        fused_tile<F>(d, b, d.list[pos], d.lmeta[pos]);
     }
 }
 
@@ -506,9 +505,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
         const int pos = slice_pos(n_active, slot);
         if (pos < 0) break;
+        // the list entry and its level and member are loaded together
         const int G = bd.list[pos];
-        const int m = bd.tdom[G];
-        fused_tile<F>(*(const DomainDev *)&doms[m], bd.par[m] ^ flip, G - bd.base[m]);
+        const int meta = bd.lmeta[pos];
+        const int m = meta & 0xffff;
+        fused_tile<F>(*(const DomainDev *)&doms[m], bd.par[m] ^ flip, G - bd.base[m], meta >> 16);
     }
 }
 
@@ -569,7 +570,8 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
 // step parity b (the list keeps each block's tiles together and in order).
 // The counter of the other parity, read by nobody during this step, is reset
 // for the next one, so no memset is needed between steps.
-__device__ __forceinline__ void append_active(int a, int id, int tb, int *count_b, int *count_other, int *list, int cap)
+__device__ __forceinline__ void append_active(int a, int id, int meta, int tb, int *count_b, int *count_other, int *list,
+                                              int *lmeta, int cap)
 {
     __shared__ int wsum[4];
     __shared__ int base;
@@ -596,7 +598,10 @@ __device__ __forceinline__ void append_active(int a, int id, int tb, int *count_
     // step (the count would then pass cap; the first cap entries, which
     // include every active tile, are what the fused kernel reads).
     const int pos = base + before + incl - 1;
-    if (a && pos < cap) list[pos] = id;
+    if (a && pos < cap) {
+        list[pos] = id;
+        lmeta[pos] = meta;
+    }
 }
 
 // Sum of c over the workgroup added to slot `slot` of part (no atomics: each
@@ -629,8 +634,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int tb = (int)blockIdx.x - nrb;
     const int g = tb * 256 + (int)threadIdx.x;
     const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
+    const int l = (g < d.ntiles) ? level_of_tile(d, g) : 0;
     add_cells(a ? d.tcells[g] : 0, d.cells_done, tb);
-    append_active(a, g, tb, &d.count[b], &d.count[b ^ 1], d.list, d.ntiles);
+    append_active(a, g, l, tb, &d.count[b], &d.count[b ^ 1], d.list, d.lmeta, d.ntiles);
 }
 
 // The same over a batch's global tables: each member's own flags decide, and
@@ -649,15 +655,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     }
     const int tb = (int)blockIdx.x - nrb;
     const int G = tb * 256 + (int)threadIdx.x;
-    int a = 0, c = 0;
+    int a = 0, c = 0, meta = 0;
     if (G < bd.ntiles) {
         const int m = bd.tdom[G];
         const DomainDev &d = bd.doms[m];
         a = tile_active(d, G - bd.base[m], all_active);
         c = a ? d.tcells[G - bd.base[m]] : 0;
+        meta = (level_of_tile(d, G - bd.base[m]) << 16) | m;
     }
     add_cells(c, bd.cells_done, tb);
-    append_active(a, G, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list, bd.ntiles);
+    append_active(a, G, meta, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list, bd.lmeta, bd.ntiles);
 }
 
 }  // namespace

@@ -303,9 +303,9 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     size_t dep_cap = plan.dep.size();
     plan_tiles(plan, RTI_TH, SIZE_MAX);
     dep_cap = std::max(dep_cap, plan.dep.size());
-    // tile info, tile flags, active list, tile cells, control block (counts, divergence flag),
+    // tile info, tile flags, active list and its levels, tile cells, control block (counts, divergence flag),
     // computed-cell sums (one per active-list workgroup)
-    bytes += 2 * align_up((size_t)cap, kAlign) + 2 * align_up((size_t)cap * 4, kAlign) + kAlign
+    bytes += 2 * align_up((size_t)cap, kAlign) + 3 * align_up((size_t)cap * 4, kAlign) + kAlign
              + align_up(sizeof(unsigned long long) * (size_t)((cap + 255) / 256), kAlign);
     // level table, child list, tile levels, per-phase tile levels
     bytes += align_up(sizeof(LevelDev) * plan.lv.size(), kAlign) + align_up(sizeof(int32_t) * plan.lv.size(), kAlign)
@@ -361,6 +361,7 @@ int carve(rti_domain *D)
     D->dev.tinfo = D->tinfo;
     D->dev.tflag = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.list = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
+    D->dev.lmeta = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
     D->tcells = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
     D->dev.tcells = D->tcells;
     D->ctrl = reinterpret_cast<int *>(take(kAlign));

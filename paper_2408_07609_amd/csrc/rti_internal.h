@@ -100,6 +100,7 @@ struct DomainDev {
     const uint8_t *tinfo;                  // ntiles static bits (TI_*)
     uint8_t *tflag;                        // ntiles: bit0 stationary in the last step (nothing it writes changed), bit1 in the one before
     int32_t *list;                         // ntiles: active tiles of the current step
+    int32_t *lmeta;                        // ntiles: level of each listed tile (written with the list)
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
     const int32_t *tcells;                 // ntiles: cells of the level inside each tile
     unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles, summed over the steps
@@ -138,6 +139,7 @@ struct BatchDev {
     const uint8_t *par;                    // n
     int32_t n, ntiles;
     int32_t *list;                         // ntiles: active global tiles of the current step
+    int32_t *lmeta;                        // ntiles: level << 16 | member of each listed tile (written with the list)
     int32_t *count;                        // [flip]
     unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles of all members
     int32_t nring;                         // ring cells of all members
