@@ -225,7 +225,9 @@ def check_plan(sc, th, name):
     G = Grid(sc, th)
     assert len(tinfo) == G.ntiles
     assert not (tinfo & TI_PINNED).any(), "a coupled-tile list did not fit its reservation"
-    assert (np.diff(off) >= 0).all() and off[-1] == len(dep)
+    assert (np.diff(off) >= 0).all() and off[0] == 0 and off[-1] == len(dep)
+    # the kernels index the flag array with these entries directly
+    assert ((dep >= 0) & (dep < G.ntiles)).all(), "a coupled-tile entry lies outside the tile table"
     n_dep_tiles = 0
     for l, L in enumerate(G.lv):
         for ty in range(L["ty"]):
