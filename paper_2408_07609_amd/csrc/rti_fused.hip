@@ -618,6 +618,12 @@ __device__ __forceinline__ void add_cells(int c, unsigned long long *part, int s
     }
 }
 
+// Ring cells per ring workgroup: one wavefront of each 256-thread workgroup
+// works, so the ring gathers spread over four times as many compute units.  A
+// vertical ring's gathers touch one cache line per lane and load, so a compute
+// unit's address units, not bytes, bound the ring half of the launch.
+#define RTI_RING_LANES 64
+
 // The active-list launch: its first nrb workgroups compute the ring means of
 // the step (one thread per ring cell; dispatched first, their gathers are the
 // longest), the others list the active tiles (one thread per tile).  Held to
@@ -627,8 +633,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                                                                                          int nrb)
 {
     if ((int)blockIdx.x < nrb) {
-        const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
-        if (e < d.nring) ring_mean<F>(d, b, e);
+        const int e = (int)blockIdx.x * RTI_RING_LANES + (int)threadIdx.x;
+        if ((int)threadIdx.x < RTI_RING_LANES && e < d.nring) ring_mean<F>(d, b, e);
         return;
     }
     const int tb = (int)blockIdx.x - nrb;
@@ -646,8 +652,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                                                                                                int all_active, int nrb)
 {
     if ((int)blockIdx.x < nrb) {
-        const int E = (int)blockIdx.x * 256 + (int)threadIdx.x;
-        if (E < bd.nring) {
+        const int E = (int)blockIdx.x * RTI_RING_LANES + (int)threadIdx.x;
+        if ((int)threadIdx.x < RTI_RING_LANES && E < bd.nring) {
             const int m = bd.rdom[E];
             ring_mean<F>(bd.doms[m], bd.par[m] ^ flip, E - bd.rbase[m]);
         }
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s)
 {
-    const int nrb = (d.nring + 255) / 256, ntb = (d.ntiles + 255) / 256;
+    const int nrb = (d.nring + RTI_RING_LANES - 1) / RTI_RING_LANES, ntb = (d.ntiles + 255) / 256;
     if (d.bulk32)
         hipLaunchKernelGGL(k_active<float>, dim3(nrb + ntb), dim3(256), 0, s, d, b, all_active, nrb);
     else
@@ -681,7 +687,7 @@ hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t 
 
 hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s)
 {
-    const int nrb = (bd.nring + 255) / 256, ntb = (bd.ntiles + 255) / 256;
+    const int nrb = (bd.nring + RTI_RING_LANES - 1) / RTI_RING_LANES, ntb = (bd.ntiles + 255) / 256;
     if (bulk32)
         hipLaunchKernelGGL(k_active_batch<float>, dim3(nrb + ntb), dim3(256), 0, s, bd, flip, all_active, nrb);
     else
