@@ -70,6 +70,10 @@ def _bind(L):
     L.ora_set_source.restype = None
     L.ora_threads.argtypes = []
     L.ora_threads.restype = ctypes.c_int
+    L.ora_cbrt_rn.argtypes = [ctypes.c_double]
+    L.ora_cbrt_rn.restype = ctypes.c_double
+    L.ora_cbrt_rn_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    L.ora_cbrt_rn_array.restype = None
     return L
 
 
@@ -88,6 +92,15 @@ def lib():
             L = ctypes.CDLL(_LIB_PATH)
             _LIB = _bind(L)
     return _LIB
+
+
+def cbrt_rn(x, lib=None):
+    """The oracle's correctly rounded cube root, element by element (x > 0)."""
+    L = lib if lib is not None else globals()["lib"]()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    y = np.empty_like(x)
+    L.ora_cbrt_rn_array(x.ctypes.data, y.ctypes.data, x.size)
+    return y
 
 
 def threads() -> int:

@@ -31,7 +31,12 @@
  * h > 0 is still-water depth, h <= 0 is land with elevation -h.
  *
  * Arithmetic: IEEE binary64, round to nearest, built with -ffp-contract=off so
- * no multiply-add is fused.  Sums are grouped exactly as written.
+ * no multiply-add is fused.  Sums are grouped exactly as written.  Every
+ * operation of the step is correctly rounded: +, -, *, / and sqrt by IEEE, and
+ * the cube root of the friction term by ora_cbrt_rn (libm's cbrt is not), so
+ * the step's result is one fixed double for each input, whatever machine
+ * computes it.  The initial condition (ora_set_source) uses libm's exp, sin and
+ * cos, which are not correctly rounded: it is exact only to within an ulp or so.
  *
  * Parity unpinned (no pin beyond the lake-at-rest, symmetry and the oracle
  * itself fixes them, because the paper is silent): the one-wet-side face depth
@@ -77,6 +82,86 @@ int ora_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Correctly rounded cube root: the double nearest to the real cube root of x,
+ * for a positive normal x (here the reciprocal of a face depth).  libm's cbrt
+ * lands within about an ulp of the root but is not always the nearest double,
+ * and another platform's cbrt need not agree with it; the nearest double is
+ * one fixed number.  Starting from libm's value y, y moves to its neighbour
+ * while the root lies beyond the midpoint between them.  The root lies above a
+ * midpoint m exactly when m^3 < x.  That test is done on integers: m = K 2^(e-1)
+ * with K odd and below 2^55, x = X 2^ex with X the 53-bit significand, and K^3
+ * (below 2^165) is compared with X 2^(ex - 3e + 3).  K^3 is odd and the other
+ * side even, so the two are never equal: no root is ever a midpoint. */
+
+/* x = X 2^E, X the 53-bit integer significand (x positive and normal). */
+static uint64_t int_significand(double x, int *E)
+{
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    *E = (int)(b >> 52) - 1075;
+    return (b & ((UINT64_C(1) << 52) - 1)) | (UINT64_C(1) << 52);
+}
+
+static double bits_step(double y, int k)         /* the k-th neighbour of y > 0 */
+{
+    uint64_t b;
+    memcpy(&b, &y, sizeof b);
+    b += (uint64_t)(int64_t)k;
+    memcpy(&y, &b, sizeof y);
+    return y;
+}
+
+/* Is ((lo + hi) / 2)^3 < x, for adjacent positive normal doubles lo < hi?
+ * Exact, on integers. */
+static int midpoint_cube_below_exact(double lo, double hi, double x)
+{
+    int elo, ehi, ex;
+    const uint64_t Llo = int_significand(lo, &elo), Lhi = int_significand(hi, &ehi), X = int_significand(x, &ex);
+    const int e = (elo < ehi) ? elo : ehi;
+    const uint64_t K = (Llo << (elo - e)) + (Lhi << (ehi - e));      /* lo + hi = K 2^e */
+    const int sh = ex - (3 * e - 3);             /* x = (X 2^sh) 2^(3e-3), midpoint^3 = K^3 2^(3e-3) */
+    if (sh < 64 || sh - 64 > 74) abort();        /* outside what the comparison was sized for */
+    /* K^3 = top 2^64 + (something below 2^64) */
+    const unsigned __int128 K2 = (unsigned __int128)K * K;                    /* below 2^110 */
+    const unsigned __int128 low = (unsigned __int128)(uint64_t)K2 * K;        /* below 2^119 */
+    const unsigned __int128 top = (K2 >> 64) * K + (low >> 64);
+    /* X 2^sh = (X 2^(sh-64)) 2^64 exactly; K^3 < X 2^sh iff top < X 2^(sh-64) */
+    return top < ((unsigned __int128)X << (sh - 64));
+}
+
+/* The same test, first in long double (64-bit significand: the midpoint is
+ * exact and its cube within 2^-63 relative), which settles every case where
+ * the cube is more than 2^-60 x away from x; the rest go to the integer test. */
+static int midpoint_cube_below(double lo, double hi, double x)
+{
+    const long double m = ((long double)lo + (long double)hi) * 0.5L;
+    const long double d = (m * m) * m - (long double)x;
+    const long double tol = 0x1p-60L * (long double)x;
+    if (d < -tol) return 1;
+    if (d > tol) return 0;
+    return midpoint_cube_below_exact(lo, hi, x);
+}
+
+double ora_cbrt_rn(double x)
+{
+    double y = cbrt(x);
+    for (int moves = 0; moves < 8; moves++) {  /* libm is within an ulp: one move at most */
+        const double up = bits_step(y, 1), dn = bits_step(y, -1);
+        if (midpoint_cube_below(y, up, x)) { y = up; continue; }      /* root above (y+up)/2 */
+        if (!midpoint_cube_below(dn, y, x)) { y = dn; continue; }     /* root below (dn+y)/2 */
+        return y;
+    }
+    return NAN;                                  /* not reached for a positive normal x */
+}
+
+/* ora_cbrt_rn over an array (for the tests of the cube root). */
+void ora_cbrt_rn_array(const double *x, double *y, int64_t n)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; k++) y[k] = ora_cbrt_rn(x[k]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -214,6 +299,19 @@ static double upwind_diff(double s, double v, int okm, double sm, double vm,
     return (-a) + b;
 }
 
+/* Semi-implicit Manning factor of a face (reading): with the face's own flux
+ * f, the cross flux c averaged to the face and the reciprocal rD = 1/D of the
+ * total depth, F = fc sqrt(f^2 + c^2) D^(-7/3), where fc = dt/2 g n^2 and
+ * D^(-7/3) = rD^2 cbrt(rD) with the correctly rounded cube root.  A face
+ * without flow has F = 0 (the product is +0 either way, so the cube root is
+ * not needed there). */
+static double friction(double fc, double f, double c, double rD)
+{
+    const double s = fc * sqrt(f * f + c * c);
+    if (!(s > 0.0)) return s;
+    return s * ((rD * rD) * ora_cbrt_rn(rD));
+}
+
 /* x-momentum, Eq. (2), at interior x-face (i,j), 1 <= i <= nx-1.
  * Time levels (reading): the level is eta^{n+1} (already updated), the fluxes
  * on the right-hand side are the old ones, M^{n+1/2}, N^{n+1/2}.
@@ -224,9 +322,11 @@ static double upwind_diff(double s, double v, int okm, double sm, double vm,
  *              x-faces (upwind_diff).
  *  friction  : Manning, g n^2 M sqrt(M^2+N^2) / D^{7/3}, semi-implicit
  *              (reading): the friction on M is the average of the old and new
- *              M, the magnitude uses the old fluxes; D^{7/3} = D^2 cbrt(D).
+ *              M, the magnitude uses the old fluxes (friction()).
  *              With F = dt/2 g n^2 sqrt(M^2+N^2)/D^{7/3}:
- *              M_new = ((1-F) M - pressure - advection) / (1+F). */
+ *              M_new = ((1-F) M - pressure - advection) / (1+F).
+ * Every quotient by a face depth is a product with that face's reciprocal
+ * depth 1/D (one division per face; reading: the paper gives no arithmetic). */
 static double xmomentum(const ora_domain *d, const ora_level *L, int i, int j)
 {
     const double eps = d->eps;
@@ -236,6 +336,7 @@ static double xmomentum(const ora_domain *d, const ora_level *L, int i, int j)
     const double r = d->dt / L->dx;
     const double gr = d->g * r;
     const double fc = 0.5 * d->dt * d->g * d->manning * d->manning;
+    const double rD = 1.0 / D;
     const double m = L->M[XF(L, i, j)];
     const double nb = nbar_at_xface(L, i, j);
 
@@ -247,20 +348,20 @@ static double xmomentum(const ora_domain *d, const ora_level *L, int i, int j)
     const int okp = (i + 1 <= L->nx - 1) && xface_depth(L, eps, i + 1, j, &Dp);
     const double mm = okm ? L->M[XF(L, i - 1, j)] : 0.0;
     const double mp = okp ? L->M[XF(L, i + 1, j)] : 0.0;
-    const double X = upwind_diff(m, (m * m) / D,
-                                 okm, mm, okm ? (mm * mm) / Dm : 0.0,
-                                 okp, mp, okp ? (mp * mp) / Dp : 0.0);
+    const double X = upwind_diff(m, (m * m) * rD,
+                                 okm, mm, okm ? (mm * mm) * (1.0 / Dm) : 0.0,
+                                 okp, mp, okp ? (mp * mp) * (1.0 / Dp) : 0.0);
     /* along y: the x-faces in rows j-1 and j+1 */
     double Ds, Dn;
     const int oks = (j - 1 >= 0) && xface_depth(L, eps, i, j - 1, &Ds);
     const int okn = (j + 1 <= L->ny - 1) && xface_depth(L, eps, i, j + 1, &Dn);
     const double nbs = oks ? nbar_at_xface(L, i, j - 1) : 0.0;
     const double nbn = okn ? nbar_at_xface(L, i, j + 1) : 0.0;
-    const double Y = upwind_diff(nb, (m * nb) / D,
-                                 oks, nbs, oks ? (L->M[XF(L, i, j - 1)] * nbs) / Ds : 0.0,
-                                 okn, nbn, okn ? (L->M[XF(L, i, j + 1)] * nbn) / Dn : 0.0);
+    const double Y = upwind_diff(nb, (m * nb) * rD,
+                                 oks, nbs, oks ? (L->M[XF(L, i, j - 1)] * nbs) * (1.0 / Ds) : 0.0,
+                                 okn, nbn, okn ? (L->M[XF(L, i, j + 1)] * nbn) * (1.0 / Dn) : 0.0);
     const double A = r * (X + Y);
-    const double F = (fc * sqrt(m * m + nb * nb)) / ((D * D) * cbrt(D));
+    const double F = friction(fc, m, nb, rD);
     return (((1.0 - F) * m - P) - A) / (1.0 + F);
 }
 
@@ -275,6 +376,7 @@ static double ymomentum(const ora_domain *d, const ora_level *L, int i, int j)
     const double r = d->dt / L->dx;
     const double gr = d->g * r;
     const double fc = 0.5 * d->dt * d->g * d->manning * d->manning;
+    const double rD = 1.0 / D;
     const double n = L->N[YF(L, i, j)];
     const double mb = mbar_at_yface(L, i, j);
 
@@ -286,20 +388,20 @@ static double ymomentum(const ora_domain *d, const ora_level *L, int i, int j)
     const int okn = (j + 1 <= L->ny - 1) && yface_depth(L, eps, i, j + 1, &Dn);
     const double ns = oks ? L->N[YF(L, i, j - 1)] : 0.0;
     const double nn = okn ? L->N[YF(L, i, j + 1)] : 0.0;
-    const double Yd = upwind_diff(n, (n * n) / D,
-                                  oks, ns, oks ? (ns * ns) / Ds : 0.0,
-                                  okn, nn, okn ? (nn * nn) / Dn : 0.0);
+    const double Yd = upwind_diff(n, (n * n) * rD,
+                                  oks, ns, oks ? (ns * ns) * (1.0 / Ds) : 0.0,
+                                  okn, nn, okn ? (nn * nn) * (1.0 / Dn) : 0.0);
     /* along x: the y-faces in columns i-1 and i+1 */
     double Dw, De;
     const int okw = (i - 1 >= 0) && yface_depth(L, eps, i - 1, j, &Dw);
     const int oke = (i + 1 <= L->nx - 1) && yface_depth(L, eps, i + 1, j, &De);
     const double mbw = okw ? mbar_at_yface(L, i - 1, j) : 0.0;
     const double mbe = oke ? mbar_at_yface(L, i + 1, j) : 0.0;
-    const double Xd = upwind_diff(mb, (n * mb) / D,
-                                  okw, mbw, okw ? (L->N[YF(L, i - 1, j)] * mbw) / Dw : 0.0,
-                                  oke, mbe, oke ? (L->N[YF(L, i + 1, j)] * mbe) / De : 0.0);
+    const double Xd = upwind_diff(mb, (n * mb) * rD,
+                                  okw, mbw, okw ? (L->N[YF(L, i - 1, j)] * mbw) * (1.0 / Dw) : 0.0,
+                                  oke, mbe, oke ? (L->N[YF(L, i + 1, j)] * mbe) * (1.0 / De) : 0.0);
     const double A = r * (Yd + Xd);
-    const double F = (fc * sqrt(n * n + mb * mb)) / ((D * D) * cbrt(D));
+    const double F = friction(fc, n, mb, rD);
     return (((1.0 - F) * n - P) - A) / (1.0 + F);
 }
 

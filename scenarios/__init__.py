@@ -252,6 +252,18 @@ def c3(scale: int = 1, seed: int = 3) -> Scenario:
     return sc
 
 
+def c3_nearshore(seed: int = 3) -> Scenario:
+    """Configuration 3's five levels and bathymetry with the 3 m, 100 x 50 km
+    uplift moved to 30 km offshore (its landward edge 5 km from the coast), so
+    that the finest levels flood within the first 600 s: a full-size wet/dry
+    workload short enough for the oracle to run as a parity reference."""
+    sc = c3(seed=seed)
+    src = sc.source
+    sc.name = "c3-nested5-nearshore"
+    sc.source = Source(src.xc + 120e3, src.yc, src.a, src.b, src.theta, src.amp, src.shape)
+    return sc
+
+
 # ---------------------------------------------------------------------------
 def _block_tree(sc: Scenario, coast, tree):
     """Append blocks level by level.  tree: one list per finer resolution of

@@ -1,13 +1,15 @@
-"""Write tests/golden/c2_full_run.npz: sampled outputs of the CPU oracle after
-the whole of configuration 2 (4 levels, 10.02 M cells, 3 m uplift, 18,000
-steps of 0.2 s = 3600 s), for the GPU full-run parity test.
+"""Write the oracle references of the GPU full-run parity tests.
 
-Only the oracle and the seeded generator are called.  Per level the file holds
-the seeded sample of cell indices, eta, the maxima, M and N at those indices,
-and whole-level sums and extrema.  The oracle source hash is stored so a test
-can tell a stale file.
+Only the oracle and the seeded generators are called.  Each file holds, per
+level, the SHA-256 of the whole final eta, M, N and maxima arrays (float64,
+row-major, as the oracle's arrays are laid out), the values at a stratified
+sample of cells and faces (every parent cell of every child's ring, every
+child edge face, the cells within 2 of the final shoreline, and random cells),
+whole-level sums and extrema, and the count of inundated land cells; and the
+SHA-256 of the oracle source that wrote it.
 
-    python tests/golden/make_golden.py          # about an hour on 8 cores
+    python tests/golden/make_golden.py c2    # configuration 2, all 18,000 steps (about 1.5 h on 8 cores)
+    python tests/golden/make_golden.py c3w   # configuration 3's grid, near-shore source, 3000 steps (about 1 h)
 """
 from __future__ import annotations
 
@@ -24,8 +26,14 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import scenarios  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_full_run.npz")
-SAMPLES = 4096
+HERE = os.path.dirname(os.path.abspath(__file__))
+CASES = {
+    # name: (scenario, steps (None: the configuration's whole run), file)
+    "c2": (lambda: scenarios.c2(), None, "c2_full_run.npz"),
+    "c3w": (lambda: scenarios.c3_nearshore(), 3000, "c3_nearshore_3000.npz"),
+}
+RANDOM = 4096
+SHORE_CAP = 8192
 
 
 def oracle_hash():
@@ -33,32 +41,89 @@ def oracle_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def main():
-    sc = scenarios.c2()
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()
+
+
+def ring_cells(sc, k):
+    """(i, j) of level k's cells on the ring of every child's footprint."""
+    out = []
+    for c, lv in enumerate(sc.levels):
+        if lv["parent"] != k:
+            continue
+        fw, fh = lv["nx"] // 3, lv["ny"] // 3
+        for J in range(fh):
+            for I in range(fw):
+                if I in (0, fw - 1) or J in (0, fh - 1):
+                    out.append((lv["off_i"] + I, lv["off_j"] + J))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
+def shoreline_band(h, e, eps, rng):
+    """Cells within 2 cells of a wet/dry change in the final state (at most SHORE_CAP, drawn at random)."""
+    wet = (h + e) > eps
+    ny, nx = wet.shape
+    pad = np.pad(wet, 2, mode="edge")
+    anyw = np.zeros_like(wet)
+    allw = np.ones_like(wet)
+    for dj in range(5):
+        for di in range(5):
+            w = pad[dj:dj + ny, di:di + nx]
+            anyw |= w
+            allw &= w
+    idx = np.flatnonzero(anyw & ~allw)
+    if idx.size > SHORE_CAP:
+        idx = np.sort(rng.choice(idx, size=SHORE_CAP, replace=False))
+    return idx
+
+
+def main(name):
+    make, steps, fname = CASES[name]
+    sc = make()
+    steps = sc.steps if steps is None else steps
     o = oracle.OracleDomain(**sc.oracle_kwargs())
     o.set_source(*sc.source.astuple())
     t0 = time.time()
-    chunk = 500
-    while o.steps < sc.steps:
-        o.step(min(chunk, sc.steps - o.steps))
-        print(f"{o.steps}/{sc.steps} steps, {time.time() - t0:.0f} s", flush=True)
-    rng = np.random.default_rng(2024)
-    out = dict(steps=np.int64(o.steps), oracle_sha256=np.array(oracle_hash()), threads=np.int64(oracle.threads()))
+    while o.steps < steps:
+        o.step(min(250, steps - o.steps))
+        print(f"{name}: {o.steps}/{steps} steps, {time.time() - t0:.0f} s", flush=True)
+    rng = np.random.default_rng(2025)
+    out = dict(steps=np.int64(o.steps), oracle_sha256=np.array(oracle_hash()), threads=np.int64(oracle.threads()),
+               scenario=np.array(sc.name), seconds=np.float64(time.time() - t0))
     for k, lv in enumerate(sc.levels):
         e, M, N = o.get_state(k)
         z = o.max_inundation(k)
+        h = lv["h"]
         ny, nx = e.shape
-        idx = rng.choice(nx * ny, size=min(SAMPLES, nx * ny), replace=False)
-        j, i = np.divmod(idx, nx)
-        out[f"l{k}_i"], out[f"l{k}_j"] = i, j
+        out[f"l{k}_sha"] = np.array([sha(e), sha(M), sha(N), sha(z)])
+        rc = ring_cells(sc, k)
+        cells = np.concatenate([rc[:, 1] * nx + rc[:, 0],
+                                shoreline_band(h, e, sc.dry_eps, rng),
+                                rng.choice(nx * ny, size=min(RANDOM, nx * ny), replace=False)])
+        cells = np.unique(cells)
+        j, i = np.divmod(cells, nx)
+        out[f"l{k}_cell"] = cells
         out[f"l{k}_eta"], out[f"l{k}_zmax"] = e[j, i], z[j, i]
-        out[f"l{k}_M"], out[f"l{k}_N"] = M[j, i], N[j, i]
+        # faces: a child's edge faces (those the parent injects) and random interior faces
+        if lv["parent"] >= 0:
+            jm = np.arange(ny)
+            mx = np.concatenate([jm * (nx + 1), jm * (nx + 1) + nx])
+            iN = np.arange(nx)
+            ny_ = np.concatenate([iN, ny * nx + iN])
+        else:
+            mx, ny_ = np.zeros(0, np.int64), np.zeros(0, np.int64)
+        mx = np.unique(np.concatenate([mx, rng.choice(M.size, size=RANDOM, replace=False)]))
+        ny_ = np.unique(np.concatenate([ny_, rng.choice(N.size, size=RANDOM, replace=False)]))
+        out[f"l{k}_mface"], out[f"l{k}_M"] = mx, M.reshape(-1)[mx]
+        out[f"l{k}_nface"], out[f"l{k}_N"] = ny_, N.reshape(-1)[ny_]
         out[f"l{k}_stats"] = np.array([e.sum(), np.abs(e).max(), z.max(), np.abs(M).max(), np.abs(N).max()])
-        land = lv["h"] <= 0
-        out[f"l{k}_inundated"] = np.int64(np.count_nonzero(land & (z > 0.01)))
-    np.savez_compressed(OUT, **out)
-    print(f"wrote {OUT} after {time.time() - t0:.0f} s", flush=True)
+        out[f"l{k}_inundated"] = np.int64(np.count_nonzero((h <= 0) & (z > 0.01)))
+        print(f"level {k}: {rc.shape[0]} ring cells, {cells.size} cells, {mx.size} + {ny_.size} faces, "
+              f"{int(out[f'l{k}_inundated'])} inundated", flush=True)
+    path = os.path.join(HERE, fname)
+    np.savez_compressed(path, **out)
+    print(f"wrote {path} after {time.time() - t0:.0f} s", flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "c2")

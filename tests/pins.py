@@ -519,6 +519,139 @@ def pin_validation(lib=None, quick=False):
     assert oracle.validate([ok, deep_child], 810.0, 1.0) == oracle.ECFL   # 270 < sqrt(2 g 4000) = 280
 
 
-ALL = [pin_lake_at_rest, pin_closed_mass, pin_nested_mass, pin_dispersion, pin_standing_period,
+# ---------------------------------------------------------------------------
+def cbrt_hard_cases(n, seed):
+    """Inputs whose cube root lies within about 2^-106 of a midpoint between
+    two adjacent doubles, with the correctly rounded roots: for y < y' adjacent
+    (y in [0.5, 4), plus the binade edges around 1 and 2), x is the double
+    nearest to m^3, m = (y + y')/2, and the nearest double to x^(1/3) is y' when
+    x > m^3 and y when x < m^3 (never equal), decided on exact rationals."""
+    from fractions import Fraction
+    rng = np.random.default_rng(seed)
+    ys = [float(v) for v in rng.uniform(0.5, 4.0, size=max(n - 4, 0))]
+    ys += [1.0, 2.0, float(np.nextafter(1.0, 0.0)), float(np.nextafter(2.0, 0.0))]
+    xs, want = [], []
+    for y in ys[:n]:
+        yu = float(np.nextafter(y, np.inf))
+        m = (Fraction(y) + Fraction(yu)) / 2
+        x = float(m ** 3)                              # Fraction -> nearest double
+        xs.append(x)
+        want.append(yu if Fraction(x) > m ** 3 else y)
+    return np.array(xs), np.array(want)
+
+
+def pin_cbrt_rn(lib=None, quick=False):
+    """The friction term's cube root is the double nearest to the real cube
+    root (correct rounding is a plain definition, so it is checked against
+    arithmetic that does not come from the oracle):
+    - exact cubes k^3 2^(3e) give k 2^e exactly;
+    - the hardest inputs, x = the double nearest to a midpoint m^3 between two
+      adjacent doubles y < y': the root then lies within about 2^-106 of m, and
+      whether it is above m (answer y') or below (answer y) is read off the
+      exact rational x - m^3;
+    - random depths' reciprocals and log-uniform values against mpmath at 200
+      bits (10^6 values, 10^5 with quick)."""
+    import mpmath
+    rng = np.random.default_rng(97)
+    # exact cubes
+    k = rng.integers(1, 1 << 17, size=2000).astype(np.float64)
+    e = rng.integers(-60, 60, size=2000)
+    x = np.ldexp(k ** 3, 3 * e)
+    got = oracle.cbrt_rn(x, lib=lib)
+    assert np.array_equal(got, np.ldexp(k, e)), "cube root of an exact cube is not exact"
+    # near-midpoint inputs
+    xs, want = cbrt_hard_cases(4000 if quick else 20000, seed=98)
+    got = oracle.cbrt_rn(xs, lib=lib)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"near-midpoint cube roots wrong at {bad.size} of {xs.size} inputs, e.g. x={xs[bad[0]]!r}"
+    # random values against mpmath
+    mpmath.mp.prec = 200
+    n = 100_000 if quick else 1_000_000
+    depth = rng.uniform(0.01, 6000.0, size=n // 2)
+    xr = np.concatenate([1.0 / depth, np.exp2(rng.uniform(-1000.0, 1000.0, size=n - n // 2))])
+    got = oracle.cbrt_rn(xr, lib=lib)
+    ref = np.array([float(mpmath.cbrt(mpmath.mpf(float(v)))) for v in xr])
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, f"cube root differs from mpmath at {bad.size} of {n} values, e.g. x={xr[bad[0]]!r}"
+
+
+# ---------------------------------------------------------------------------
+def _source_at(lib, x, y, src, h=1000.0):
+    """The initial level that set_source gives a cell centred at (x, y), and
+    its starting maximum (a 3 x 3 level whose middle cell sits there)."""
+    dx = 100.0
+    hh = np.full((3, 3), h)
+    d = dom([lvl(hh)], dx, 0.1, lib=lib, x0=x - 1.5 * dx, y0=y - 1.5 * dx)
+    d.set_source(*src)
+    return d.level(0)["eta"][1, 1], d.level(0)["zmax"][1, 1]
+
+
+def pin_source(lib=None, quick=False):
+    """The initial sea-surface displacement follows its definition (Sec. II-A
+    gives the fault model no form; the reading: a Gaussian amp exp(-rho^2/2),
+    or an elliptic uplift amp cos^2(pi rho / 2) inside rho < 1, with
+    rho^2 = (x'/a)^2 + (y'/b)^2 and (x', y') the offset from the centre
+    rotated by theta, so a and b are the semi-axes along theta and
+    theta + 90 degrees).  Checked at points placed by hand: the centre, the
+    ends of both semi-axes, half-way along an axis, just inside and outside
+    the ellipse; the field is unchanged when theta grows by pi; land cells
+    hold eta = -h (no water) and a displacement below the ground is clipped."""
+    xc, yc, a, b, th, amp = 3.0e5, 2.0e5, 5.0e4, 2.0e4, 0.4, 3.0
+    ca, sa = math.cos(th), math.sin(th)
+    along = lambda t: (xc + t * a * ca, yc + t * a * sa)        # t semi-axes along theta
+    across = lambda t: (xc - t * b * sa, yc + t * b * ca)       # t semi-axes along theta + 90 deg
+    gauss = (xc, yc, a, b, th, amp, 0)
+    ell = (xc, yc, a, b, th, amp, 1)
+    close = lambda v, w, tol=1e-13: abs(v - w) <= tol * abs(amp)
+    for src in (gauss, ell):
+        e, z = _source_at(lib, xc, yc, src)
+        assert e == amp and z == amp, f"shape {src[6]}: centre {e}"
+    for pt in (along(1.0), along(-1.0), across(1.0), across(-1.0)):
+        e, _ = _source_at(lib, *pt, gauss)
+        assert close(e, amp * math.exp(-0.5)), f"Gaussian at a semi-axis end: {e} vs {amp * math.exp(-0.5)}"
+    for pt in (along(0.5), across(-0.5)):
+        e, _ = _source_at(lib, *pt, ell)
+        assert close(e, 0.5 * amp), f"uplift half-way along an axis: {e} vs {0.5 * amp}"
+    for pt in (along(1.001), across(1.001), along(-1.001)):
+        e, _ = _source_at(lib, *pt, ell)
+        assert e == 0.0, f"uplift outside the ellipse: {e}"
+    for pt in (along(0.999), across(0.999)):
+        e, _ = _source_at(lib, *pt, ell)
+        want = amp * math.cos(0.5 * math.pi * 0.999) ** 2
+        assert close(e, want, 1e-9), f"uplift just inside the ellipse: {e} vs {want}"
+    # off-axis point: (0.6, 0.5) semi-axes gives rho^2 = 0.61
+    px, py = xc + 0.6 * a * ca - 0.5 * b * sa, yc + 0.6 * a * sa + 0.5 * b * ca
+    e, _ = _source_at(lib, px, py, gauss)
+    assert close(e, amp * math.exp(-0.5 * 0.61)), f"Gaussian off the axes: {e}"
+    # theta + pi describes the same ellipse
+    rng = np.random.default_rng(5)
+    n = 24
+    h = np.full((n, n), 2000.0)
+    for shape in (0, 1):
+        f = []
+        for t in (th, th + math.pi):
+            d = dom([lvl(h)], 4000.0, 1.0, lib=lib)
+            d.set_source(n * 2000.0 + 1234.5, n * 2000.0 - 777.0, 3.0e4, 1.5e4, t, amp, shape)
+            f.append(d.level(0)["eta"].copy())
+        assert np.abs(f[0] - f[1]).max() <= 1e-12 * amp, f"shape {shape}: theta and theta + pi differ"
+        assert np.abs(f[0]).max() > 0.5 * amp
+    # land keeps -h even under an uplift higher than the land (amp 30 m over
+    # land up to 20 m); a trough deeper than a shallow sea cell is clipped to
+    # its ground
+    h = rng.uniform(-20.0, 3000.0, size=(n, n))
+    h[::5, ::3] = 0.5                                  # shallow sea cells
+    h[n // 2 - 2:n // 2 + 2, ::2] = -5.0               # land under the middle of the source
+    land = h <= 0
+    for amp_k in (30.0, -2.0):
+        d = dom([lvl(h)], 4000.0, 1.0, lib=lib)
+        d.set_source(n * 2000.0, n * 2000.0, 4.0e4, 3.0e4, 0.0, amp_k, 1)
+        e, z = d.level(0)["eta"], d.level(0)["zmax"]
+        assert np.array_equal(e[land], -h[land]) and np.array_equal(z[land], np.zeros(land.sum())), "land cells"
+        assert np.array_equal(z[~land], e[~land]), "sea maxima start at eta"
+        assert np.all(h + e >= 0.0)
+    assert np.any((h > 0) & (h + e == 0.0)), "shallow cells under the trough not clipped"
+
+
+ALL = [pin_cbrt_rn, pin_source, pin_lake_at_rest, pin_closed_mass, pin_nested_mass, pin_dispersion, pin_standing_period,
        pin_wave_speed, pin_mirror_symmetry, pin_nested_symmetry, pin_friction_ode, pin_consistency,
        pin_dam_break, pin_max_tracking, pin_jnz_linear, pin_open_boundary, pin_validation]

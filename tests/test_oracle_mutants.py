@@ -33,14 +33,24 @@ MUTANTS = {
         "if (s > 0.0) return okp ? vp - v : 0.0;\n    if (s < 0.0) return okm ? v - vm : 0.0;"),
     "advection: dropped cross term": ("const double A = r * (X + Y);", "const double A = r * X;"),
     "advection: cross flux uses M twice": (
-        "const double Y = upwind_diff(nb, (m * nb) / D,", "const double Y = upwind_diff(nb, (m * m) / D,"),
+        "const double Y = upwind_diff(nb, (m * nb) * rD,", "const double Y = upwind_diff(nb, (m * m) * rD,"),
+    "advection: neighbour quotient by the face's own depth": (
+        "okm ? (mm * mm) * (1.0 / Dm) : 0.0", "okm ? (mm * mm) * rD : 0.0"),
     "advection: N average index": (
         "return 0.25 * ((L->N[YF(L, i - 1, j)] + L->N[YF(L, i - 1, j + 1)])",
         "return 0.25 * ((L->N[YF(L, i - 1, j)] + L->N[YF(L, i - 1, j)])"),
     "friction: factor 1 instead of 1/2": (
         "const double fc = 0.5 * d->dt * d->g * d->manning * d->manning;",
         "const double fc = d->dt * d->g * d->manning * d->manning;"),
-    "friction: D^(4/3)": ("((D * D) * cbrt(D))", "(D * cbrt(D))"),
+    "friction: D^(4/3)": ("return s * ((rD * rD) * ora_cbrt_rn(rD));", "return s * (rD * ora_cbrt_rn(rD));"),
+    "cube root: libm's value kept": ("    double y = cbrt(x);\n    for (int moves", "    double y = cbrt(x);\n    return y;\n    for (int moves"),
+    "cube root: midpoint exponent": ("const int sh = ex - (3 * e - 3);", "const int sh = ex - (3 * e - 2);"),
+    "source: rotation sign": (
+        "double xp = ddx * ct + ddy * st;\n                double yp = -(ddx * st) + ddy * ct;",
+        "double xp = ddx * ct - ddy * st;\n                double yp = ddx * st + ddy * ct;"),
+    "source: a and b as full axes": ("double u = xp / a, v = yp / b;", "double u = xp / (0.5 * a), v = yp / (0.5 * b);"),
+    "source: Gaussian scale": ("s = amp * exp(-0.5 * rho2);", "s = amp * exp(-rho2);"),
+    "source: land cells get the displacement": ("double e = (h > 0.0) ? s : -h;", "double e = s;"),
     "child->parent: transposed parent cell": (
         "size_t pc = CELL(P, C->off_i + I, C->off_j + J);", "size_t pc = CELL(P, C->off_j + J, C->off_i + I);"),
     "child->parent: dry cells in the mean": (
@@ -58,7 +68,7 @@ MUTANTS = {
     "maxima: level instead of depth on land": ("double v = (h > 0.0) ? e : h + e;", "double v = e;"),
 }
 
-BATTERY = [pins.pin_lake_at_rest, pins.pin_closed_mass, pins.pin_nested_mass, pins.pin_jnz_linear,
+BATTERY = [pins.pin_cbrt_rn, pins.pin_source, pins.pin_lake_at_rest, pins.pin_closed_mass, pins.pin_nested_mass, pins.pin_jnz_linear,
            pins.pin_max_tracking, pins.pin_open_boundary, pins.pin_dispersion, pins.pin_mirror_symmetry,
            pins.pin_friction_ode, pins.pin_dam_break, pins.pin_consistency]
 
