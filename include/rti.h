@@ -263,6 +263,19 @@ int rti_batch_cell_updates(rti_batch *batch, int64_t *all, int64_t *computed);
  * stepped alone again).  NULL is a no-op.  Synchronises first. */
 void rti_batch_destroy(rti_batch *batch);
 
+/* Diagnostic: the FP64 operations the step is built from, applied element by
+ * element, so that a test can compare them with IEEE binary64 (the step's
+ * FP64 results are bitwise reproducible only because each of them is
+ * correctly rounded).  op: RTI_PROBE_CBRT, the cube root of the Manning term
+ * (Eqs. 2-3: D^(-7/3) = (1/D)^2 cbrt(1/D)), defined for positive normal x;
+ * RTI_PROBE_RECIP, the reciprocal 1/x of a face depth; RTI_PROBE_SQRT, the
+ * square root.  x and y are device arrays of n doubles (y may alias x); the
+ * kernel is enqueued on hip_stream (borrowed, NULL = default stream) and the
+ * call returns without waiting.  RTI_EINVAL for an unknown op, n < 0 or a NULL
+ * array with n > 0. */
+enum { RTI_PROBE_CBRT = 0, RTI_PROBE_RECIP = 1, RTI_PROBE_SQRT = 2 };
+int rti_math_probe(int32_t op, const double *x, double *y, int64_t n, void *hip_stream);
+
 const char *rti_last_error(void);
 const char *rti_strerror(int code);
 

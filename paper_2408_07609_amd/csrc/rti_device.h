@@ -53,14 +53,8 @@ __device__ __forceinline__ double radiate(double g, double eps, double h, double
     return sign * (c * e);
 }
 
-// 1/x: the hardware reciprocal refined by one Newton step (x is a positive
-// depth or 1 + F, far from denormals).
-__device__ __forceinline__ double recip(double x)
-{
-    const double r = __builtin_amdgcn_rcp(x);
-    const double e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
+// FP32-bulk helpers.  1/x: the hardware reciprocal refined by one Newton
+// step (x is a positive depth or 1 + F, far from denormals).
 __device__ __forceinline__ float recip(float x)
 {
     const float r = __builtin_amdgcn_rcpf(x);
@@ -68,19 +62,7 @@ __device__ __forceinline__ float recip(float x)
     return fmaf(r, e, r);
 }
 
-// x^(-1/3) for x > 0: a binary32 estimate z = 2^(-log2(x)/3) (relative error
-// d below 1e-6), then one correction of second order.  With e = 1 - x z^3
-// (about -3d), the exact value is z (1 - e)^(-1/3) = z (1 + e/3 + 2e^2/9 +
-// O(e^3)); the dropped O(e^3) term is below 1e-17 relative, so the result is
-// within about 1.5 ulp of binary64.
-__device__ __forceinline__ double rcbrt(double x)
-{
-    const double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)x));
-    const double z3 = (z * z) * z;
-    const double e = fma(-x, z3, 1.0);
-    const double c = fma(e, 2.0 / 9.0, 1.0 / 3.0);
-    return fma(z * e, c, z);
-}
+// x^(-1/3) for x > 0 in binary32: 2^(-log2(x)/3) and one Newton step.
 __device__ __forceinline__ float rcbrt(float x)
 {
     float z = __builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf(x));
@@ -88,21 +70,74 @@ __device__ __forceinline__ float rcbrt(float x)
     return (z * (4.0f - x * z3)) * (1.0f / 3.0f);
 }
 
-// sqrt(x) for x >= 0 (0 for x = 0): the hardware reciprocal square root y
-// refined by one Goldschmidt step on (g, h) = (x y, y/2) and one residual
-// correction g += (x - g^2) h; within about 1 ulp of the rounded root.
-__device__ __forceinline__ double sqrt_nonneg(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    const double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    const double d = fma(-g, g, x);
-    g = fma(d, h, g);
-    return (x > 0.0) ? g : 0.0;
-}
 __device__ __forceinline__ float sqrt_nonneg(float x) { return sqrtf(x); }
+
+// ---------------------------------------------------------------------------
+// FP64: correctly rounded operations only, so that every result is the one
+// fixed double that IEEE binary64 defines.  1/x and sqrt are the language's
+// operators (IEEE division and square root on gfx950); the cube root, which
+// has no correctly rounded library form, is cbrt_rn below.
+
+// Is ((lo + hi) / 2)^3 < a, exactly?  For adjacent doubles lo < hi in
+// [0.5, 2) and a in [0.5, 4): such doubles are integer multiples of 2^-53, so
+// lo + hi = K 2^-53 with K < 2^55, the midpoint is K 2^-54, and a = A 2^-53
+// with A < 2^55.  The test is K^3 < A 2^109, on 192-bit integers (three
+// 64-bit words).  K^3 is odd and A 2^109 even, so they never tie.
+__device__ __forceinline__ bool midpoint_cube_below(double lo, double hi, double a)
+{
+    const uint64_t K = (uint64_t)(lo * 0x1p53) + (uint64_t)(hi * 0x1p53);
+    const uint64_t A = (uint64_t)(a * 0x1p53);
+    const uint64_t k2l = K * K, k2h = __umul64hi(K, K);             // K^2 = k2h 2^64 + k2l, k2h < 2^46
+    const uint64_t l_lo = k2l * K, l_hi = __umul64hi(k2l, K);        // k2l K
+    const uint64_t h_lo = k2h * K, h_hi = __umul64hi(k2h, K);        // k2h K, h_hi < 2^37
+    const uint64_t w1 = h_lo + l_hi;                                 // K^3 = w2 2^128 + w1 2^64 + l_lo
+    const uint64_t w2 = h_hi + (w1 < l_hi ? 1u : 0u);
+    const uint64_t b2 = A >> 19, b1 = A << 45;                       // A 2^109 = b2 2^128 + b1 2^64
+    (void)l_lo;
+    return (w2 < b2) || (w2 == b2 && w1 < b1);
+}
+
+// Cube root of a positive normal double, correctly rounded (the double
+// nearest to the real root).  x = a 2^(3q) with a in [0.5, 4).  An estimate
+// z of a^(-1/3) from binary32 log2/exp2 (relative error about 2^-22) gets a
+// correction of second order: with e = 1 - a z^3, a^(-1/3) = z (1 - e)^(-1/3)
+// = z (1 + e/3 + 2e^2/9 + O(e^3)), leaving an error near 2^-52.  y = a z^2
+// is then within a few ulps of the root, and d = (a - y^3) / (3 y^2), with the
+// residual a - y^3 formed from the exact products y^2 = p + pl and
+// p y = t + tl, is the distance from y to the root to about 2^-50 relative.
+// s = y + d rounded is the nearest double unless the root lies within 2^-21
+// ulp of the midpoint between s and its neighbour on that side (err, the
+// exact rounding error of y + d, says how close); that case is settled by
+// the exact test midpoint_cube_below.
+__device__ __forceinline__ double cbrt_rn(double x)
+{
+    const int ex = __builtin_amdgcn_frexp_exp(x);                    // x = m 2^ex, m in [0.5, 1)
+    const int q = (ex + 1023) / 3 - 341;                             // floor(ex / 3)
+    const double a = __builtin_amdgcn_ldexp(__builtin_amdgcn_frexp_mant(x), ex - 3 * q);
+    double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)a));
+    const double e = fma(-a, (z * z) * z, 1.0);
+    z = fma(z * e, fma(e, 2.0 / 9.0, 1.0 / 3.0), z);
+    const double y = (a * z) * z;
+    const double p = y * y, pl = fma(y, y, -p);
+    const double t = p * y, tl = fma(p, y, -t);
+    const double res = ((a - t) - tl) - pl * y;
+    const double d = res * ((z * z) * (1.0 / 3.0));
+    const double s = y + d;
+    const double err = d - (s - y);                                  // exact (|d| << |y|)
+    const long long bits = __double_as_longlong(s);
+    const double nb = __longlong_as_double(err > 0.0 ? bits + 1 : bits - 1);
+    const double half = 0.5 * (nb - s);                              // exact, signed
+    double r = s;
+    if (fabs(err) > fabs(half) * (1.0 - 0x1p-20)) {
+        const bool above_mid = (err > 0.0) ? midpoint_cube_below(s, nb, a) : midpoint_cube_below(nb, s, a);
+        r = (err > 0.0) ? (above_mid ? nb : s) : (above_mid ? s : nb);
+    }
+    return __builtin_amdgcn_ldexp(r, q);
+}
+
+// Reciprocal of a face depth: IEEE division in FP64.
+__device__ __forceinline__ double inv_depth(double D) { return 1.0 / D; }
+__device__ __forceinline__ float inv_depth(float D) { return recip(D); }
 
 // Momentum flux quantity a*b/D given 1/D.
 template <typename F>
@@ -111,19 +146,39 @@ __device__ __forceinline__ F over_depth(F a, F b, F invD)
     return (a * b) * invD;
 }
 
-// New flux of an active face: ((1-F) f - Pr - A) / (1+F) with Pr = (gr D) de,
-// A = r (along + cross) and the semi-implicit Manning factor
-// F = (dt/2) g n^2 sqrt(f^2 + cr^2) / D^(7/3), D^(-7/3) = (D^(-1/3))^7.
-template <typename F>
-__device__ __forceinline__ F momentum_update(F f, F cr, F D, F de, F along, F cross, F r, F gr, F fc)
+// Semi-implicit Manning factor of a face, F = fc sqrt(f^2 + c^2) D^(-7/3)
+// (fc = dt/2 g n^2, f the face's flux, c the cross flux averaged to the face).
+// FP64: D^(-7/3) = iD^2 cbrt(iD), iD = 1/D, every operation correctly rounded.
+// FP32-bulk: D^(-7/3) = z^7 with z = D^(-1/3).
+__device__ __forceinline__ double friction(double fc, double f, double c, double D, double iD)
 {
-    const F Pr = (gr * D) * de;
-    const F A = r * (along + cross);
-    const F z = rcbrt(D);
-    const F z2 = z * z;
-    const F z7 = (z2 * z2) * (z2 * z);
-    const F Fr = (fc * sqrt_nonneg(f * f + cr * cr)) * z7;
-    return (((F(1) - Fr) * f - Pr) - A) * recip(F(1) + Fr);
+    (void)D;
+    return (fc * sqrt(f * f + c * c)) * ((iD * iD) * cbrt_rn(iD));
+}
+__device__ __forceinline__ float friction(float fc, float f, float c, float D, float iD)
+{
+    (void)iD;
+    const float z = rcbrt(D);
+    const float z2 = z * z;
+    return (fc * sqrt_nonneg(f * f + c * c)) * ((z2 * z2) * (z2 * z));
+}
+
+// New flux of an active face: ((1-Fr) f - Pr - A) / (1+Fr) with Pr = (gr D) de,
+// A = r (along + cross) and Fr the Manning factor (friction).  FP64 divides;
+// FP32-bulk multiplies by the refined reciprocal.
+__device__ __forceinline__ double momentum_update(double f, double Fr, double D, double de, double along,
+                                                  double cross, double r, double gr)
+{
+    const double Pr = (gr * D) * de;
+    const double A = r * (along + cross);
+    return (((1.0 - Fr) * f - Pr) - A) / (1.0 + Fr);
+}
+__device__ __forceinline__ float momentum_update(float f, float Fr, float D, float de, float along,
+                                                 float cross, float r, float gr)
+{
+    const float Pr = (gr * D) * de;
+    const float A = r * (along + cross);
+    return (((1.0f - Fr) * f - Pr) - A) * recip(1.0f + Fr);
 }
 
 }  // namespace rti_dev

@@ -83,28 +83,30 @@ struct FaceQ {
     F cr;         // the cross flux averaged to the face (N on x-faces, M on y-faces)
     F q;          // f^2 / D
     F p;          // f * cr / D
+    F fr;         // Manning factor of the face (friction)
     int act;      // face active under the wet/dry rule (and interior)
 };
 
 // The wet/dry rule and the depth are evaluated in FP64 on the FP64 levels.
 template <typename F>
 __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, double hb, double eb, double eps,
-                                          F f, F cr)
+                                          F f, F cr, F fc)
 {
     // Computed on every lane.  An inactive face carries D = 1 (a safe value)
-    // and q, p of that D; nothing reads them: neighbours test act first, and
-    // the face's own new flux is replaced by 0.
+    // and q, p, fr of that D; nothing reads them: neighbours test act first,
+    // and the face's own new flux is replaced by 0.
     FaceQ<F> o;
     double D;
     const bool act = face_depth(ha, ea, hb, eb, eps, D) & interior;
     const F Df = act ? (F)D : F(1);
-    const F iD = recip(Df);
+    const F iD = inv_depth(Df);
     o.act = act ? 1 : 0;
     o.D = Df;
     o.f = f;
     o.cr = cr;
     o.q = over_depth(f, f, iD);
     o.p = over_depth(f, cr, iD);
+    o.fr = friction(fc, f, cr, Df, iD);
     return o;
 }
 
@@ -124,9 +126,9 @@ struct RowW {
 // New flux of an active face (momentum_update); de is the FP64 water-level
 // difference across the face.
 template <typename F>
-__device__ __forceinline__ F new_flux(const FaceQ<F> &m, double de, F along, F cross, F r, F gr, F fc)
+__device__ __forceinline__ F new_flux(const FaceQ<F> &m, double de, F along, F cross, F r, F gr)
 {
-    return momentum_update<F>(m.f, m.cr, m.D, (F)de, along, cross, r, gr, fc);
+    return momentum_update(m.f, m.fr, m.D, (F)de, along, cross, r, gr);
 }
 
 // Child-to-parent mean of ring cell e of the domain (Sec. IV-C): the mean of
@@ -365,9 +367,9 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
         cur.HL = from_left(H_t);
         cur.NyL = from_left(cur.Ny);
         const F nb = F(0.25) * ((p.NyL + cur.NyL) + (p.Ny + cur.Ny));
-        cur.x = face_q<F>(col_xint && row_cell, cur.HL, cur.e1L, H_t, e1, eps, cur.Mx, nb);
+        cur.x = face_q<F>(col_xint && row_cell, cur.HL, cur.e1L, H_t, e1, eps, cur.Mx, nb, fcf);
         const F mb = F(0.25) * ((p.Mx + p.MxR) + (cur.Mx + cur.MxR));
-        cur.y = face_q<F>(col_cell && t >= 1 && t <= ny - 1, p.H, p.e1, H_t, e1, eps, p.Ny, mb);
+        cur.y = face_q<F>(col_cell && t >= 1 && t <= ny - 1, p.H, p.e1, H_t, e1, eps, p.Ny, mb, fcf);
 
         // Momentum and outputs of row (x-faces, cells) / face (y-faces) rr = t-1.
         // The momentum of both faces is evaluated on every lane (inactive
@@ -384,10 +386,10 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
             const F yl_p = from_left(yp.p), yr_p = from_right(yp.p);
             const F X = upwind_diff<F>(xp.f, xp.q, xl_act != 0, xl_f, xl_q, xr_act != 0, xr_f, xr_q);
             const F Y = upwind_diff<F>(xp.cr, xp.p, pp.x.act != 0, pp.x.cr, pp.x.p, cur.x.act != 0, cur.x.cr, cur.x.p);
-            const F Mint = new_flux<F>(xp, p.e1 - p.e1L, X, Y, rf, grf, fcf);
+            const F Mint = new_flux<F>(xp, p.e1 - p.e1L, X, Y, rf, grf);
             const F Yd = upwind_diff<F>(yp.f, yp.q, pp.y.act != 0, pp.y.f, pp.y.q, cur.y.act != 0, cur.y.f, cur.y.q);
             const F Xd = upwind_diff<F>(yp.cr, yp.p, yl_act != 0, yl_cr, yl_p, yr_act != 0, yr_cr, yr_p);
-            const F Nint = new_flux<F>(yp, p.e1 - pp.e1, Yd, Xd, rf, grf, fcf);
+            const F Nint = new_flux<F>(yp, p.e1 - pp.e1, Yd, Xd, rf, grf);
             const bool xf_here = col_xf && rr < ny;
             const bool yf_int = col_cell && rr >= 1 && rr <= ny - 1;
             F Mnew = (xp.act != 0) ? Mint : F(0);        // xp.act implies an interior face
@@ -471,7 +473,7 @@ __device__ __forceinline__ int slice_pos(int n_active, int slot)
 
 // One workgroup per active tile.
 template <typename F>
-__global__ __launch_bounds__(64) void k_fused(DomainDev d, int b)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused(DomainDev d, int b)
 {
     const int pos = slice_pos(min(d.count[b], d.ntiles), (int)(blockIdx.x >> 3));
     if (pos >= 0) fused_tile<F>(d, b, d.list[pos], d.lmeta[pos]);

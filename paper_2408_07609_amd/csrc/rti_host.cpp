@@ -928,6 +928,15 @@ int rti_step(rti_domain *D, int64_t nsteps)
     }
 }
 
+int rti_math_probe(int32_t op, const double *x, double *y, int64_t n, void *hip_stream)
+{
+    if (op < RTI_PROBE_CBRT || op > RTI_PROBE_SQRT) return fail(RTI_EINVAL, "probe op %d unknown", op);
+    if (n < 0 || n > (int64_t)0x7fffffff * 256) return fail(RTI_EINVAL, "n %lld outside [0, 2^31 * 256)", (long long)n);
+    if (n > 0 && (!x || !y)) return fail(RTI_EINVAL, "NULL array");
+    HIP_TRY(launch_probe_math(op, x, y, n, static_cast<hipStream_t>(hip_stream)));
+    return RTI_OK;
+}
+
 int rti_sync(rti_domain *D)
 {
     if (!D) return fail(RTI_EINVAL, "domain is NULL");

@@ -174,3 +174,4 @@ hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t 
 hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
 hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s);
 hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s);
+hipError_t launch_probe_math(int op, const double *x, double *y, int64_t n, hipStream_t s);

@@ -52,7 +52,7 @@ __device__ __forceinline__ double mbar_y(const View &v, int i, int j)
 
 // x-momentum at interior x-face (i,j): M_new = ((1-F) M - Pr - A) / (1+F) with
 // Pr = (gr D)(eta_i - eta_{i-1}), A = r (X + Y), F = fc sqrt(M^2+Nb^2) D^(-7/3)
-// (momentum_update); the quotients by depths use 1/D (over_depth).
+// (friction, momentum_update); the quotients by depths use 1/D (over_depth).
 __device__ double xmom(const View &v, double eps, double r, double gr, double fc, int i, int j)
 {
     double D;
@@ -61,15 +61,15 @@ __device__ double xmom(const View &v, double eps, double r, double gr, double fc
     const double m = v.M[i + P * j];
     const double nb = nbar_x(v, i, j);
 
-    const double iD = recip(D);
+    const double iD = inv_depth(D);
 
     double Dm = 0.0, Dp = 0.0;
     const bool okm = (i - 1 >= 1) && xdepth(v, eps, i - 1, j, Dm);
     const bool okp = (i + 1 <= v.nx - 1) && xdepth(v, eps, i + 1, j, Dp);
     const double mm = okm ? v.M[(i - 1) + P * j] : 0.0;
     const double mp = okp ? v.M[(i + 1) + P * j] : 0.0;
-    const double X = upwind_diff(m, over_depth(m, m, iD), okm, mm, okm ? over_depth(mm, mm, recip(Dm)) : 0.0,
-                                 okp, mp, okp ? over_depth(mp, mp, recip(Dp)) : 0.0);
+    const double X = upwind_diff(m, over_depth(m, m, iD), okm, mm, okm ? over_depth(mm, mm, inv_depth(Dm)) : 0.0,
+                                 okp, mp, okp ? over_depth(mp, mp, inv_depth(Dp)) : 0.0);
 
     double Ds = 0.0, Dn = 0.0;
     const bool oks = (j - 1 >= 0) && xdepth(v, eps, i, j - 1, Ds);
@@ -77,9 +77,9 @@ __device__ double xmom(const View &v, double eps, double r, double gr, double fc
     const double nbs = oks ? nbar_x(v, i, j - 1) : 0.0;
     const double nbn = okn ? nbar_x(v, i, j + 1) : 0.0;
     const double Y = upwind_diff(nb, over_depth(m, nb, iD), oks, nbs,
-                                 oks ? over_depth(v.M[i + P * (j - 1)], nbs, recip(Ds)) : 0.0, okn, nbn,
-                                 okn ? over_depth(v.M[i + P * (j + 1)], nbn, recip(Dn)) : 0.0);
-    return momentum_update(m, nb, D, v.eta[i + P * j] - v.eta[(i - 1) + P * j], X, Y, r, gr, fc);
+                                 oks ? over_depth(v.M[i + P * (j - 1)], nbs, inv_depth(Ds)) : 0.0, okn, nbn,
+                                 okn ? over_depth(v.M[i + P * (j + 1)], nbn, inv_depth(Dn)) : 0.0);
+    return momentum_update(m, friction(fc, m, nb, D, iD), D, v.eta[i + P * j] - v.eta[(i - 1) + P * j], X, Y, r, gr);
 }
 
 // y-momentum at interior y-face (i,j): the mirror of xmom (x<->y, M<->N).
@@ -91,15 +91,15 @@ __device__ double ymom(const View &v, double eps, double r, double gr, double fc
     const double n = v.N[i + P * j];
     const double mb = mbar_y(v, i, j);
 
-    const double iD = recip(D);
+    const double iD = inv_depth(D);
 
     double Ds = 0.0, Dn = 0.0;
     const bool oks = (j - 1 >= 1) && ydepth(v, eps, i, j - 1, Ds);
     const bool okn = (j + 1 <= v.ny - 1) && ydepth(v, eps, i, j + 1, Dn);
     const double ns = oks ? v.N[i + P * (j - 1)] : 0.0;
     const double nn = okn ? v.N[i + P * (j + 1)] : 0.0;
-    const double Yd = upwind_diff(n, over_depth(n, n, iD), oks, ns, oks ? over_depth(ns, ns, recip(Ds)) : 0.0,
-                                  okn, nn, okn ? over_depth(nn, nn, recip(Dn)) : 0.0);
+    const double Yd = upwind_diff(n, over_depth(n, n, iD), oks, ns, oks ? over_depth(ns, ns, inv_depth(Ds)) : 0.0,
+                                  okn, nn, okn ? over_depth(nn, nn, inv_depth(Dn)) : 0.0);
 
     double Dw = 0.0, De = 0.0;
     const bool okw = (i - 1 >= 0) && ydepth(v, eps, i - 1, j, Dw);
@@ -107,9 +107,9 @@ __device__ double ymom(const View &v, double eps, double r, double gr, double fc
     const double mbw = okw ? mbar_y(v, i - 1, j) : 0.0;
     const double mbe = oke ? mbar_y(v, i + 1, j) : 0.0;
     const double Xd = upwind_diff(mb, over_depth(n, mb, iD), okw, mbw,
-                                  okw ? over_depth(v.N[(i - 1) + P * j], mbw, recip(Dw)) : 0.0, oke, mbe,
-                                  oke ? over_depth(v.N[(i + 1) + P * j], mbe, recip(De)) : 0.0);
-    return momentum_update(n, mb, D, v.eta[i + P * j] - v.eta[i + P * (j - 1)], Yd, Xd, r, gr, fc);
+                                  okw ? over_depth(v.N[(i - 1) + P * j], mbw, inv_depth(Dw)) : 0.0, oke, mbe,
+                                  oke ? over_depth(v.N[(i + 1) + P * j], mbe, inv_depth(De)) : 0.0);
+    return momentum_update(n, friction(fc, n, mb, D, iD), D, v.eta[i + P * j] - v.eta[i + P * (j - 1)], Yd, Xd, r, gr);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,7 +292,25 @@ __global__ __launch_bounds__(256) void k_init_level(LevelDev L, InitSource sp)
     static_cast<F *>(L.zmax)[c] = (F)((h > 0.0) ? eta : h + eta);
 }
 
+// The FP64 operations the step is built from, element by element, for the
+// tests that compare them with IEEE binary64: op 0 cube root (cbrt_rn), 1 the
+// reciprocal of a depth (inv_depth), 2 the square root.
+__global__ __launch_bounds__(256) void k_probe_math(int op, const double *x, double *y, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const double v = x[k];
+    y[k] = (op == 0) ? cbrt_rn(v) : (op == 1) ? inv_depth(v) : sqrt(v);
+}
+
 }  // namespace
+
+hipError_t launch_probe_math(int op, const double *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_math, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, op, x, y, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s)
 {

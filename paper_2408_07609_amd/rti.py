@@ -24,6 +24,7 @@ RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
 RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED, RTI_FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 RTI_MAX_LEVELS = 128
 RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX, RTI_TILE_ROWS_DEFAULT = 4, 64, 12
+RTI_PROBE_CBRT, RTI_PROBE_RECIP, RTI_PROBE_SQRT = 0, 1, 2
 
 _dptr = ctypes.POINTER(ctypes.c_double)
 
@@ -86,6 +87,8 @@ FUNCTIONS = {
     "rti_batch_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "rti_batch_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dptr, _dptr, _dptr]),
     "rti_batch_destroy": (None, [ctypes.c_void_p]),
+    "rti_math_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]),
     "rti_last_error": (ctypes.c_char_p, []),
     "rti_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -133,6 +136,22 @@ def rti_domain_create(desc: rti_domain_desc, arena_ptr: int | None, arena_bytes:
     out = ctypes.c_void_p(0)
     _check(LIB.rti_domain_create(ctypes.byref(desc), arena_ptr, arena_bytes, stream_ptr, ctypes.byref(out)))
     return out.value
+
+
+def rti_math_probe(op: int, x_ptr: int, y_ptr: int, n: int, stream_ptr: int | None):
+    _check(LIB.rti_math_probe(op, x_ptr, y_ptr, n, stream_ptr))
+
+
+def math_probe(op: int, x):
+    """The library's FP64 operation `op` (RTI_PROBE_*) applied to a float64
+    device tensor x on torch's current stream; returns a new tensor."""
+    import torch
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError("x must be a float64 device tensor")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    rti_math_probe(op, x.data_ptr(), y.data_ptr(), x.numel(), torch.cuda.current_stream().cuda_stream)
+    return y
 
 
 def rti_set_source(dom: int, src: rti_source):

@@ -132,3 +132,10 @@ def test_tile_and_batch_calls_validate_before_the_gpu():
     assert ei.value.code == rti.RTI_EINVAL
     rti.rti_batch_destroy(None)                          # NULL is a no-op
     assert rti.RTI_TILE_ROWS_MIN <= rti.RTI_TILE_ROWS_DEFAULT <= rti.RTI_TILE_ROWS_MAX
+
+
+def test_math_probe_rejects_bad_arguments():
+    assert rti.LIB.rti_math_probe(7, None, None, 0, None) == rti.RTI_EINVAL
+    assert rti.LIB.rti_math_probe(rti.RTI_PROBE_CBRT, None, None, -1, None) == rti.RTI_EINVAL
+    assert rti.LIB.rti_math_probe(rti.RTI_PROBE_SQRT, None, None, 5, None) == rti.RTI_EINVAL
+    assert rti.LIB.rti_math_probe(rti.RTI_PROBE_RECIP, None, None, 0, None) == rti.RTI_OK   # nothing to do

@@ -1,10 +1,15 @@
 """HIP path against the CPU oracle, through the C ABI, on the same seeded inputs.
 
-Bar (FP64): max |d eta| <= 1e-9 m after a full run on every cell of every
-level, the same bound on the maxima, and fluxes within 1e-9 of their scale.
-The two sides evaluate the same formulas operation by operation without
-fused multiply-adds; they can differ by rounding only through cbrt (device
-and host libraries), so single steps agree to a few ulp.
+Bar (FP64): every operation of the step is correctly rounded on both sides
+(IEEE +, -, *, /, sqrt; a correctly rounded cube root on each side), the
+formulas are evaluated operation by operation in the same order with no fused
+multiply-add, so from the same state the two give the same bits: eta, M, N and
+the maxima are compared for bitwise equality on every cell and face of every
+level (which implies the required max |d eta| <= 1e-9 m, checked first).
+The initial condition is the one part that is not exact: both sides evaluate
+the source with their own exp, sin and cos (not correctly rounded), so a run
+that starts from each side's own rti_set_source is held to the 1e-9 m bar
+only, and the bitwise runs start the GPU from the oracle's initial level.
 """
 import numpy as np
 import pytest
@@ -48,6 +53,21 @@ def assert_close(ds, tol=TOL, what=""):
         assert d["M"] <= tol and d["N"] <= tol, f"{what} level {k}: {d}"
 
 
+def assert_bitwise(d, o, nlev, what=""):
+    for k in range(nlev):
+        for name, x, y in zip(("eta", "M", "N", "max"), d.get_state(k) + (d.max_inundation(k),),
+                              o.get_state(k) + (o.max_inundation(k),)):
+            assert np.array_equal(x, y), f"{what} level {k}: {name} not bitwise equal (max {np.abs(x - y).max():.3e})"
+
+
+def start_from_oracle_source(d, o, sc):
+    """The oracle's rti_set_source counterpart, copied to the GPU as a raw
+    initial level (fluxes zero, maxima start there, like rti_set_source)."""
+    o.set_source(*sc.source.astuple())
+    for k in range(len(sc.levels)):
+        d.set_eta(k, o.get_state(k)[0])
+
+
 def set_random(d, o, sc, seed, flux=5.0):
     for k, (e, M, N) in enumerate(scenarios.random_state(sc, seed, flux=flux)):
         h = sc.levels[k]["h"]
@@ -67,7 +87,8 @@ def test_one_step_random_state(nlev):
     set_random(d, o, sc, seed=5)
     d.step(1)
     o.step(1)
-    assert_close(diffs(d, o, nlev), tol=1e-12, what=f"one step nlev={nlev}")
+    assert_close(diffs(d, o, nlev), what=f"one step nlev={nlev}")
+    assert_bitwise(d, o, nlev, what=f"one step nlev={nlev}")
 
 
 def test_steps_random_state_graph_and_eager_agree():
@@ -84,11 +105,32 @@ def test_steps_random_state_graph_and_eager_agree():
         eb, Mb, Nb = b.get_state(k)
         assert np.array_equal(ea, eb) and np.array_equal(Ma, Mb) and np.array_equal(Na, Nb)
     assert_close(diffs(a, o, 3), what="45 steps from a random state")
+    assert_bitwise(a, o, 3, what="45 steps from a random state")
+
+
+def test_set_source_matches_oracle():
+    """rti_set_source against the oracle's source on every level: land cells
+    and cells outside the uplift exactly, the displacement within a few ulp
+    of its amplitude (each side's own exp, sin and cos)."""
+    for sc in (scenarios.c1(), scenarios.small_nested(seed=7, nlev=3), scenarios.c2(scale=10)):
+        d, o = gpu_domain(sc), ora_domain(sc)
+        d.set_source(*sc.source.astuple())
+        o.set_source(*sc.source.astuple())
+        amp = abs(sc.source.amp)
+        for k in range(len(sc.levels)):
+            e, M, N = d.get_state(k)
+            eo = o.get_state(k)[0]
+            h = sc.levels[k]["h"]
+            assert np.array_equal(e[h <= 0], eo[h <= 0]) and np.array_equal(e[eo == 0.0], eo[eo == 0.0])
+            assert np.abs(e - eo).max() <= 8e-16 * amp, f"{sc.name} level {k}: {np.abs(e - eo).max()}"
+            assert np.abs(d.max_inundation(k) - o.max_inundation(k)).max() <= 8e-16 * amp
+            assert not M.any() and not N.any()
 
 
 def test_c1_full_run():
     """Configuration 1: 256x256 at 810 m, shelf and shoals, 2 m hump, open
-    sides, 1000 steps of 1 s."""
+    sides, 1000 steps of 1 s.  From each side's own source: within 1e-9 m;
+    from the oracle's initial level: bitwise."""
     sc = scenarios.c1()
     d, o = gpu_domain(sc), ora_domain(sc)
     d.set_source(*sc.source.astuple())
@@ -100,17 +142,22 @@ def test_c1_full_run():
     assert_close(ds, what="c1 full run")
     z = o.max_inundation(0)
     assert z.max() > 0.5
+    d2 = gpu_domain(sc)
+    start_from_oracle_source(d2, o2 := ora_domain(sc), sc)
+    d2.run(sc.steps * sc.dt)
+    o2.run(sc.steps * sc.dt)
+    assert_bitwise(d2, o2, 1, what="c1 full run from the oracle's initial level")
 
 
 def test_small_nested_source_run():
     sc = scenarios.small_nested(seed=7, nlev=3)
     d, o = gpu_domain(sc), ora_domain(sc)
-    d.set_source(*sc.source.astuple())
-    o.set_source(*sc.source.astuple())
+    start_from_oracle_source(d, o, sc)
     d.step(3000)
     o.step(3000)
     ds = diffs(d, o, 3)
     assert_close(ds, what="small nested 3000 steps")
+    assert_bitwise(d, o, 3, what="small nested 3000 steps")
     land = sc.levels[2]["h"] <= 0
     assert (o.max_inundation(2)[land] > 0.01).any(), "no inundation in the finest level"
 
@@ -121,11 +168,11 @@ def test_c2_reduced_run():
     810/270/90/30 m over the same kind of coast), 4000 steps of 0.2 s."""
     sc = scenarios.c2(scale=10)
     d, o = gpu_domain(sc), ora_domain(sc)
-    d.set_source(*sc.source.astuple())
-    o.set_source(*sc.source.astuple())
+    start_from_oracle_source(d, o, sc)
     d.step(4000)
     o.step(4000)
     assert_close(diffs(d, o, 4), what="c2/10 4000 steps")
+    assert_bitwise(d, o, 4, what="c2/10 4000 steps")
 
 
 def test_lake_at_rest_bitwise():
