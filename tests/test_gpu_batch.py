@@ -25,11 +25,12 @@ def members():
     ]
 
 
-def make(sc, flags=0, precision=None, rows=None):
+def make(sc, flags=0, precision=None, rows=None, source=True):
     from paper_2408_07609_amd import RTI_FP64, Domain
     d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
                x0=sc.x0, y0=sc.y0, flags=flags, precision=RTI_FP64 if precision is None else precision)
-    d.set_source(*sc.source.astuple())
+    if source:
+        d.set_source(*sc.source.astuple())
     if rows is not None:
         d.set_tile_rows(rows)
     return d
@@ -127,20 +128,27 @@ def test_batch_membership_changes():
 def test_batched_member_against_oracle():
     from paper_2408_07609_amd import Batch
     scs = members()
-    ds = [make(sc) for sc in scs]
-    with Batch(ds) as b:
-        b.step(300)
     sc = scs[0]
     o = oracle.OracleDomain(**sc.oracle_kwargs())
     o.set_source(*sc.source.astuple())
+    ds = [make(q) for q in scs]
+    first = make(sc, source=False)
+    for k in range(len(sc.levels)):              # the oracle's initial level (bitwise run)
+        first.set_eta(k, o.get_state(k)[0])
+    ds[0] = first
+    with Batch(ds) as b:
+        b.step(300)
     o.step(300)
     for k in range(len(sc.levels)):
         e, M, N = ds[0].get_state(k)
         eo, Mo, No = o.get_state(k)
+        z, zo = ds[0].max_inundation(k), o.max_inundation(k)
         fs = max(1.0, np.abs(Mo).max(), np.abs(No).max())
         assert np.abs(e - eo).max() <= 1e-9
-        assert np.abs(ds[0].max_inundation(k) - o.max_inundation(k)).max() <= 1e-9
+        assert np.abs(z - zo).max() <= 1e-9
         assert np.abs(M - Mo).max() / fs <= 1e-9 and np.abs(N - No).max() / fs <= 1e-9
+        for name, x, y in (("eta", e, eo), ("M", M, Mo), ("N", N, No), ("max", z, zo)):
+            assert np.array_equal(x, y), f"level {k}: {name} not bitwise equal"
 
 
 def test_batch_rules():

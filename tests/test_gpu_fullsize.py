@@ -3,7 +3,8 @@ benchmark times (fused kernel, active tiles, HIP graphs).
 
 The oracle computes every cell of a few steps from a seeded random state of
 the full grid (wet/dry mix, both flux signs, every exchange), so every output
-of those steps is compared, not a sample.  Skipping stationary tiles is checked
+of those steps is compared, not a sample: within 1e-9 m first, then for
+bitwise equality (every FP64 operation is correctly rounded on both sides).  Skipping stationary tiles is checked
 to be exact at full size against the same run with skipping off.
 """
 import numpy as np
@@ -38,10 +39,14 @@ def run_random(sc, steps, seed):
     for k in range(len(sc.levels)):
         e, M, N = d.get_state(k)
         eo, Mo, No = o.get_state(k)
+        z, zo = d.max_inundation(k), o.max_inundation(k)
         worst[k] = (float(np.abs(e - eo).max()), float(np.abs(M - Mo).max()), float(np.abs(N - No).max()),
-                    float(np.abs(d.max_inundation(k) - o.max_inundation(k)).max()))
+                    float(np.abs(z - zo).max()))
         print(f"level {k}: max|d eta| {worst[k][0]:.2e} |dM| {worst[k][1]:.2e} |dN| {worst[k][2]:.2e} "
               f"|d max| {worst[k][3]:.2e}", flush=True)
+        assert max(worst[k]) <= 1e-9, f"level {k}: {worst[k]}"
+        for name, x, y in (("eta", e, eo), ("M", M, Mo), ("N", N, No), ("max", z, zo)):
+            assert np.array_equal(x, y), f"level {k}: {name} not bitwise equal"
     d.close()
     return worst
 
