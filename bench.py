@@ -2,15 +2,23 @@
 """Throughput of the nested long-wave time step on one MI355X.
 
 One bench step = one time step of the whole nested domain (mass, child->parent
-level, momentum, parent->child flux, open sides, maxima on every level).
-Default workload: the 4-level nest at 810/270/90/30 m (1200x1000, 900^2,
-1500^2, 2400^2 = 10.02 M cells) over a seeded synthetic coast, dt = 0.2 s,
-3 m elliptic uplift, run for the whole 3600 s (18,000 steps) from t = 0,
-inputs resident in HBM.  Prints one JSON line on stdout; progress on stderr.
---config c3b: C3 split into the 84 blocks of the paper's Table 1;
---config c4: the batched ensemble (48 uneven scenarios, FP32-bulk, one batch);
---config c5: forecast serving (Poisson arrivals, continuous batching, p50/p99
-time to forecast).
+level, momentum, parent->child flux, open sides, maxima on every level), FP64.
+Default workload: configuration 3, the 5-level nest at 810/270/90/30/10 m
+(1266x1590, 1305^2, 1494^2, 3141^2, 5604^2 = 47.2 M cells, the shapes of the
+paper's Table 1) over a seeded synthetic coast with 40 % dry coastal plains,
+dt = 0.2 s, 3 m elliptic uplift, inputs resident in HBM.
+
+Timed window: with no --steps, the whole configuration (108,000 steps = 6 h
+simulated) from t = 0 with stationary tiles skipped ("full_run"); with
+--steps K shorter than that, K steps with every tile computed ("dense": no
+counted cell is skipped), after --warmup steps.  Graph capture and the first
+steps' set-up always happen before the timed window.  In the dense case the
+whole 6-hour run is measured too, in the same process, and reported as
+"full_run".  Prints one JSON line on stdout; progress on stderr.
+--config c1/c2: the smaller configurations; c3b: C3 split into the 84 blocks
+of the paper's Table 1; c4: the batched ensemble (48 uneven scenarios,
+FP32-bulk, one batch); c5: forecast serving (Poisson arrivals, continuous
+batching, p50/p99 time to forecast).
 """
 from __future__ import annotations
 
@@ -83,7 +91,20 @@ def copy_probe():
     log(f"copy probe: 3 copies of {COPY_PROBE_BYTES} bytes")
 
 
-def cpu_baseline(sc, seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(sc, seconds):
+    """The oracle (as it stands) stepping the configuration from t = 0 for
+    about `seconds` of CPU work; returns (cell-updates/s, steps, seconds, threads)."""
     import oracle
     o = oracle.OracleDomain(**sc.oracle_kwargs())
     o.set_source(*sc.source.astuple())
@@ -91,14 +112,46 @@ def cpu_baseline(sc, seconds):
     o.step(1)
     done = 1
     el = time.perf_counter() - t0
-    per = el
-    while el + per < seconds:
+    while el + el / done < seconds:
         o.step(1)
         done += 1
         el = time.perf_counter() - t0
-        per = el / done
-    return dict(value=sc.cells * done / el, unit="cell-updates/s", cores=oracle.threads(), kind="oracle",
-                sample=f"{sc.name}: all {sc.cells} cells, steps 1..{done} from t=0 ({el:.1f} s of CPU work)")
+    return sc.cells * done / el, done, el, oracle.threads()
+
+
+SCENARIOS = ("c1", "c2", "c3", "c3b")
+
+
+def scenario(name):
+    import scenarios
+    return {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3, "c3b": scenarios.c3_blocks}[name]()
+
+
+def cpu_baseline(sc, seconds, config=None):
+    """The oracle on the host's cores (OpenMP over rows, all cores), and, when
+    the configuration is named, the same on one thread in a child process."""
+    v, done, el, threads = _oracle_rate(sc, seconds)
+    out = dict(value=v, unit="cell-updates/s", cores=threads, kind="oracle",
+               sample=f"{sc.name}: all {sc.cells} cells, steps 1..{done} from t=0 ({el:.1f} s of CPU work)",
+               cpu_model=cpu_model(), nproc=os.cpu_count())
+    if config is not None:
+        import subprocess
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", config,
+                            "--cpu-seconds", str(seconds)], env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0 and r.stdout.strip():
+            out["one_thread"] = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            out["one_thread"] = {"error": (r.stderr or "")[-300:]}
+    return out
+
+
+def cpu_child(config, seconds):
+    """Child process of cpu_baseline (OMP_NUM_THREADS=1): no GPU is touched."""
+    sc = scenario(config)
+    v, done, el, threads = _oracle_rate(sc, seconds)
+    print(json.dumps(dict(value=v, unit="cell-updates/s", cores=threads,
+                          sample=f"{sc.name}: all {sc.cells} cells, steps 1..{done} from t=0 ({el:.1f} s)")))
 
 
 def make_domain(sc, precision, flags=0):
@@ -306,12 +359,198 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+GRAPH_STEPS = 20      # steps per captured HIP graph in the library
+
+
+def timed_steps(d, steps, torch):
+    """Time `steps` steps of domain d on its stream: wall clock around the
+    enqueue and a synchronisation, and HIP events recorded on d's stream."""
+    stream = d.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    all0, comp0 = d.cell_updates()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    d.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    all1, comp1 = d.cell_updates()
+    return wall, ev0.elapsed_time(ev1) / 1e3, all1 - all0, comp1 - comp0
+
+
+def full_run(sc, prec, flags, torch, np):
+    """The whole configuration from t = 0 with stationary tiles skipped: the
+    graph is captured by untimed steps first, then the state goes back to
+    t = 0 (which, like a new domain, computes every tile in the first two
+    steps) and all sc.steps steps are timed."""
+    d = make_domain(sc, prec, flags)
+    init = [d.get_state(k) for k in range(len(sc.levels))]
+    zinit = [d.max_inundation(k) for k in range(len(sc.levels))]
+    d.step(2 * GRAPH_STEPS)
+    d.sync()
+    for k, (e, M, N) in enumerate(init):
+        d.set_state(k, e, M, N)
+        d.set_max(k, zinit[k])
+    d.sync()
+    log(f"full run: {sc.steps} steps ({sc.steps * sc.dt:.0f} s simulated)")
+    wall, ev_s, all_, comp = timed_steps(d, sc.steps, torch)
+    assert all_ == sc.cells * sc.steps
+    for k in range(len(sc.levels)):
+        assert np.all(np.isfinite(d.get_state(k)[0])), "non-finite state after the full run"
+    log(f"full run: {wall:.2f} s wall, {ev_s:.2f} s by events, computed fraction {comp / all_:.3f}")
+    return d, dict(steps=sc.steps, simulated_s=sc.steps * sc.dt, wall_s=wall, events_s=ev_s,
+                   value=sc.cells * sc.steps / wall, unit="cell-updates/s", computed_cell_updates=comp,
+                   computed_fraction=comp / all_, active_cell_updates_per_s=comp / wall)
+
+
+def bench_single(args):
+    import numpy as np
+    import torch
+
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FP32_BULK, RTI_FP64
+
+    sc = scenario(args.config)
+    prec = RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64
+    bpc = BYTES_PER_CELL_FP32_BULK if prec == RTI_FP32_BULK else BYTES_PER_CELL
+    dense = args.steps is not None and args.steps < sc.steps
+    steps = args.steps if dense else sc.steps
+    log(f"workload {sc.name}: {len(sc.levels)} levels, {sc.cells} cells, "
+        f"{'dense window of ' + str(steps) if dense else 'full run of ' + str(steps)} steps, {args.precision}")
+
+    full = None
+    if dense:
+        # every tile computed; warmup (at least one graph's worth, rounded up
+        # to whole graphs so the timed window starts on a captured graph)
+        d = make_domain(sc, prec, args.flags | RTI_FLAG_NO_ACTIVE)
+        if args.tile_rows:
+            d.set_tile_rows(args.tile_rows)
+        prep = max(args.warmup, GRAPH_STEPS)
+        prep = (prep + GRAPH_STEPS - 1) // GRAPH_STEPS * GRAPH_STEPS
+        d.step(prep)
+        d.sync()
+        log(f"warmup: {prep} untimed steps (graph captured)")
+        wall, ev_s, all_, comp = timed_steps(d, steps, torch)
+        assert all_ == comp == sc.cells * steps, "the dense window skipped cells"
+        window = "dense"
+        untimed = prep
+    else:
+        d, full = full_run(sc, prec, args.flags, torch, np)
+        wall, ev_s, all_, comp = full["wall_s"], full["events_s"], sc.cells * steps, full["computed_cell_updates"]
+        window = "full_run"
+        untimed = 2 * GRAPH_STEPS
+    log(f"timed {steps} steps: {wall:.3f} s wall, {ev_s:.3f} s by events")
+    active, total, active_cells = d.active_tiles()
+
+    # kernel durations with HIP events on the domain's stream, launched one by one
+    prof, prof_cells = d.profile(args.profile_steps)
+    dom = max((k for k in prof if k in bpc), key=lambda k: prof[k])
+    launch_ms = prof[dom]
+    units = prof_cells if dom == "k_fused" else sc.cells
+    alg = bpc[dom] * units
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    log(f"kernel times (ms/launch): {prof}; cells per launch {units:.0f}")
+    d.close()
+    del d
+    if args.copy_probe:
+        copy_probe()
+    if dense and not args.no_full_run:
+        dfull, full = full_run(sc, prec, args.flags, torch, np)
+        fprof, fcells = dfull.profile(args.profile_steps)
+        full["kernel_ms_at_end"] = fprof
+        full["cells_per_launch_at_end"] = fcells
+        dfull.close()
+        del dfull
+
+    out = {
+        "metric": "cell-updates/s",
+        "value": sc.cells * steps / wall,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == RTI_FP64 else "f32-bulk (f64 water level)",
+        "data": "synthetic",
+        "config": {
+            "workload": sc.name,
+            "timed_window": window,
+            "untimed_steps_before_window": untimed,
+            "cells": sc.cells,
+            "levels": [[lv["nx"], lv["ny"]] for lv in sc.levels],
+            "dx_m": [sc.level_dx(k) for k in range(len(sc.levels))],
+            "dt_s": sc.dt,
+            "simulated_s": steps * sc.dt,
+            "active_tiles_last_step": [active, total],
+            "active_cells_last_step": active_cells,
+            "computed_cell_updates": comp,
+            "active_cell_updates_per_s": comp / wall,
+            "flags": args.flags | (RTI_FLAG_NO_ACTIVE if dense else 0),
+            "tile_rows": args.tile_rows or 12,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(dom + ("" if prec == RTI_FP64 else "_fp32bulk"), sc.name, units)
+            if dense else None,
+            "bytes_per_cell": bpc[dom],
+            "cells_per_launch": units,
+            "launch_ms": launch_ms,
+            "kernel_ms": prof,
+        },
+    }
+    if full is not None and dense:
+        out["full_run"] = full
+    if prec == RTI_FP32_BULK and not args.no_fp64:
+        out["fp32_bulk_error_vs_fp64"] = fp32_error(sc, args.flags, steps if dense else sc.steps, np)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, config=args.config)
+    print(json.dumps(out), flush=True)
+
+
+def fp32_error(sc, flags, steps, np):
+    """FP32-bulk against FP64 on the same GPU after `steps` steps from the
+    same source: max and RMS |d eta| over every cell of every level, max
+    |d maxima|, and the inundated land cells (maxima above 1 cm) of each."""
+    from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64
+    a, b = make_domain(sc, RTI_FP32_BULK, flags), make_domain(sc, RTI_FP64, flags)
+    a.step(steps)
+    b.step(steps)
+    emax = zmax = esq = 0.0
+    n = 0
+    inund = [0, 0]
+    for k, lv in enumerate(sc.levels):
+        de = np.abs(a.get_state(k)[0] - b.get_state(k)[0])
+        za, zb = a.max_inundation(k), b.max_inundation(k)
+        emax = max(emax, float(de.max()))
+        esq += float(np.sum(de * de))
+        n += de.size
+        zmax = max(zmax, float(np.abs(za - zb).max()))
+        land = lv["h"] <= 0
+        inund[0] += int(np.count_nonzero(land & (za > 0.01)))
+        inund[1] += int(np.count_nonzero(land & (zb > 0.01)))
+    a.close()
+    b.close()
+    out = {"after_steps": steps, "eta_max_m": emax, "eta_rms_m": math.sqrt(esq / max(1, n)), "maxima_max_m": zmax,
+           "inundated_cells_fp32_bulk": inund[0], "inundated_cells_fp64": inund[1]}
+    log(f"fp32-bulk error vs fp64: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole configuration)")
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3b", "c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c3b", "c4", "c5"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
     ap.add_argument("--tile-rows", type=int, default=0, help="tile height of the fused kernel (0: the library's default)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])
@@ -326,8 +565,12 @@ def main():
     ap.add_argument("--time-scale", type=float, default=30.0, help="c5: compression of arrivals and durations")
     ap.add_argument("--chunk", type=int, default=200, help="c5: batch steps between admission points")
     ap.add_argument("--hbm-gib", type=float, default=0.0, help="c5: HBM budget (default 80%% of free memory)")
+    ap.add_argument("--no-full-run", action="store_true", help="dense window only: skip the whole-run measurement")
+    ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
+    if args.cpu_child:
+        return cpu_child(args.cpu_child, args.cpu_seconds)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library drives one GPU)",
               file=sys.stderr)
@@ -340,109 +583,7 @@ def main():
             args.precision = "fp32-bulk"          # the ensemble runs in FP32-bulk unless asked otherwise
         return bench_batch(args)
 
-    import numpy as np
-    import torch
-
-    import scenarios
-    from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64, Domain
-
-    sc = {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3, "c3b": scenarios.c3_blocks}[args.config]()
-    steps = args.steps if args.steps is not None else sc.steps
-    log(f"workload {sc.name}: {len(sc.levels)} levels, {sc.cells} cells, {steps} timed steps")
-    d = Domain(sc.levels, sc.dx0, sc.dt, g=sc.g, manning_n=sc.manning_n, dry_eps=sc.dry_eps, bc=sc.bc,
-               x0=sc.x0, y0=sc.y0, flags=args.flags, device="cuda:0",
-               precision=RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64)
-    bpc = BYTES_PER_CELL_FP32_BULK if args.precision == "fp32-bulk" else BYTES_PER_CELL
-    if args.tile_rows:
-        d.set_tile_rows(args.tile_rows)
-    d.set_source(*sc.source.astuple())
-    init = [d.get_state(k) for k in range(len(sc.levels))]
-    zinit = [d.max_inundation(k) for k in range(len(sc.levels))]
-    d.step(args.warmup)
-    d.sync()
-    # back to t = 0: the timed run is the configuration itself
-    for k, (e, M, N) in enumerate(init):
-        d.set_state(k, e, M, N)
-        d.set_max(k, zinit[k])
-    log("warmup done")
-
-    stream = d.stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    all0, comp0 = d.cell_updates()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    d.step(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
-    log(f"timed {steps} steps: {wall:.3f} s wall, {ev_ms / 1e3:.3f} s by events")
-    all1, comp1 = d.cell_updates()
-    assert all1 - all0 == sc.cells * steps
-    e_last = d.get_state(len(sc.levels) - 1)[0]
-    assert np.all(np.isfinite(e_last)), "non-finite state after the timed run"
-    active, total, active_cells = d.active_tiles()
-
-    prof, prof_cells = d.profile(args.profile_steps)
-    dom = max((k for k in prof if k in bpc), key=lambda k: prof[k])
-    launch_ms = prof[dom]
-    # algorithmic bytes of one launch: the per-cell figure times the cells the
-    # launch computes (skipped stationary tiles move no data)
-    units = prof_cells if dom == "k_fused" else sc.cells
-    alg = bpc[dom] * units
-    achieved = alg / (launch_ms * 1e-3) / 1e9
-    log(f"kernel times (ms/launch): {prof}; cells per launch {units:.0f}")
-    if args.copy_probe:
-        copy_probe()
-
-    value = sc.cells * steps / wall
-    out = {
-        "metric": "cell-updates/s",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-bulk (f64 water level)",
-        "data": "synthetic",
-        "config": {
-            "workload": sc.name,
-            "cells": sc.cells,
-            "levels": [[lv["nx"], lv["ny"]] for lv in sc.levels],
-            "dx_m": [sc.level_dx(k) for k in range(len(sc.levels))],
-            "dt_s": sc.dt,
-            "simulated_s": steps * sc.dt,
-            "active_tiles": [active, total],
-            "active_cells_last_step": active_cells,
-            "computed_cell_updates": comp1 - comp0,
-            "active_cell_updates_per_s": (comp1 - comp0) / wall,
-            "flags": args.flags,
-            "tile_rows": d.tile_rows,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom + ("" if args.precision == "fp64" else "_fp32bulk"), sc.name, units),
-            "bytes_per_cell": bpc[dom],
-            "cells_per_launch": units,
-            "launch_ms": launch_ms,
-            "kernel_ms": prof,
-        },
-    }
-    d.close()
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return bench_single(args)
 
 
 if __name__ == "__main__":
