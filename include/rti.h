@@ -218,6 +218,20 @@ int rti_domain_tile_rows(const rti_domain *dom, int32_t *rows);
  * duration of the call; synchronises. */
 int rti_domain_autotune(rti_domain *dom, int32_t nsteps, int32_t *rows_out, double *ms_out);
 
+/* rti_domain_autotune for callers that cannot allocate device memory (tight
+ * serving loops that tune each arriving request, harnesses that forbid
+ * hipMalloc): the same trials and the same exact restore, but the state
+ * snapshot is staged in a static device array of RTI_AUTOTUNE_NOALLOC_MAX_BYTES
+ * that the library holds on each GPU it runs on until the process ends, and
+ * no hipMalloc, hipFree or other allocating routine is called (the timing
+ * events are the domain's own, made by rti_domain_create).  RTI_ENOMEM,
+ * before anything runs, when the domain's state is larger than the array.
+ * Every call on one GPU shares that GPU's array, whose contents the next
+ * call overwrites: calls that overlap on one GPU (from several threads, or on
+ * several streams) race and must not be made. */
+#define RTI_AUTOTUNE_NOALLOC_MAX_BYTES (128u << 20)
+int rti_domain_autotune_noalloc(rti_domain *dom, int32_t nsteps, int32_t *rows_out, double *ms_out);
+
 /* Free the domain's device memory (when the library allocated it), its
  * graphs and the handle.  NULL is a no-op.  Synchronises first.  A domain
  * still in a batch is removed from it first. */

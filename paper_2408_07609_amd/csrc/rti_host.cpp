@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -749,12 +750,18 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             delete D;
             return fail(RTI_EHIP, "querying the device failed: %s", hipGetErrorString(e));
         }
+        e = hipEventCreate(&D->tev[0]);
+        if (e == hipSuccess) e = hipEventCreate(&D->tev[1]);
+        if (e != hipSuccess) {
+            rti_domain_destroy(D);
+            return fail(RTI_EHIP, "creating the timing events failed: %s", hipGetErrorString(e));
+        }
         if (arena) {
             D->mem = arena;
         } else {
             e = hipMalloc(&D->mem, plan.bytes);
             if (e != hipSuccess) {
-                delete D;
+                rti_domain_destroy(D);
                 return fail(RTI_ENOMEM, "hipMalloc(%zu) failed: %s", plan.bytes, hipGetErrorString(e));
             }
             D->owns_mem = true;
@@ -1158,7 +1165,42 @@ int rti_domain_tile_rows(const rti_domain *D, int32_t *rows)
     return RTI_OK;
 }
 
-int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double *ms_out)
+}  // extern "C"
+
+namespace {
+
+// Staging memory of rti_domain_autotune_noalloc: a file-scope device array,
+// so each GPU that loads the library holds its own copy (its own address)
+// until the process ends, and that entry point allocates nothing.  In host
+// code the symbol is only a stand-in: the device address of this GPU's copy
+// comes from hipGetSymbolAddress, taken once per device with the device
+// current (noalloc_stage), and only that address is passed to HIP.
+__device__ __align__(256) unsigned char scratch[RTI_AUTOTUNE_NOALLOC_MAX_BYTES];
+
+std::mutex g_stage_mu;
+void *g_stage[64] = {};            // per device ordinal
+
+int noalloc_stage(int device, void **out)
+{
+    if (device < 0 || device >= 64) return fail(RTI_EINVAL, "device %d outside [0, 64)", device);
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    if (!g_stage[device]) {
+        int prev = 0;
+        HIP_TRY(hipGetDevice(&prev));
+        HIP_TRY(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess || !p) return fail(RTI_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_stage[device] = p;
+    }
+    *out = g_stage[device];
+    return RTI_OK;
+}
+
+// The autotuner.  stage: device memory of at least level_bytes for the state
+// snapshot, or null to allocate it here.
+int autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double *ms_out, void *stage)
 {
     if (!D) return fail(RTI_EINVAL, "domain is NULL");
     if (nsteps < 1) return fail(RTI_EINVAL, "nsteps %d < 1", nsteps);
@@ -1166,8 +1208,8 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
     if (D->flags & RTI_FLAG_PHASED) return fail(RTI_EINVAL, "the per-phase kernels have no tiles to tune");
     if (D->diverged) return fail(RTI_EDIVERGED, "the domain diverged earlier");
     static const int kCand[] = {4, 5, 6, 8, 10, 12, 16, 24};
-    void *snap = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    void *snap = stage;
+    hipEvent_t *ev = D->tev;
     const int cur0 = D->cur;
     const int64_t steps0 = D->steps;
     std::vector<unsigned long long> done0((size_t)(D->plan.ntiles_cap + 255) / 256);   // the trials do not count
@@ -1189,11 +1231,13 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         HIP_TRY(hipMemcpyAsync(done0.data(), D->dev.cells_done, sizeof(unsigned long long) * done0.size(),
                                hipMemcpyDeviceToHost, D->stream));
         HIP_TRY(hipStreamSynchronize(D->stream));
-        hipError_t e = hipMalloc(&snap, D->plan.level_bytes);
-        if (e != hipSuccess) return fail(RTI_ENOMEM, "autotune snapshot of %zu bytes: %s", D->plan.level_bytes, hipGetErrorString(e));
+        hipError_t e = hipSuccess;
+        if (!stage) {
+            e = hipMalloc(&snap, D->plan.level_bytes);
+            if (e != hipSuccess)
+                return fail(RTI_ENOMEM, "autotune snapshot of %zu bytes: %s", D->plan.level_bytes, hipGetErrorString(e));
+        }
         e = hipMemcpyAsync(snap, D->mem, D->plan.level_bytes, hipMemcpyDeviceToDevice, D->stream);
-        if (e == hipSuccess) e = hipEventCreate(&ev[0]);
-        if (e == hipSuccess) e = hipEventCreate(&ev[1]);
         if (e != hipSuccess) rc = fail(RTI_EHIP, "autotune set-up: %s", hipGetErrorString(e));
         bool first = true;
         for (int c : kCand) {
@@ -1248,13 +1292,32 @@ int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double
         (void)reset_counts(D);
         (void)hipStreamSynchronize(D->stream);
     }
-    for (auto &x : ev)
-        if (x) (void)hipEventDestroy(x);
-    if (snap) (void)hipFree(snap);
+    if (snap && !stage) (void)hipFree(snap);
     if (rc) return rc;
     if (rows_out) *rows_out = best;
     if (ms_out) *ms_out = best_ms;
     return RTI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rti_domain_autotune(rti_domain *D, int32_t nsteps, int32_t *rows_out, double *ms_out)
+{
+    return autotune(D, nsteps, rows_out, ms_out, nullptr);
+}
+
+int rti_domain_autotune_noalloc(rti_domain *D, int32_t nsteps, int32_t *rows_out, double *ms_out)
+{
+    if (!D) return fail(RTI_EINVAL, "domain is NULL");
+    if (D->plan.level_bytes > (size_t)RTI_AUTOTUNE_NOALLOC_MAX_BYTES)
+        return fail(RTI_ENOMEM, "the domain's state is %zu bytes, above the %zu bytes of the static staging array",
+                    D->plan.level_bytes, (size_t)RTI_AUTOTUNE_NOALLOC_MAX_BYTES);
+    void *stage = nullptr;
+    int rc = noalloc_stage(D->device, &stage);
+    if (rc) return rc;
+    return autotune(D, nsteps, rows_out, ms_out, stage);
 }
 
 void rti_domain_destroy(rti_domain *D)
@@ -1264,6 +1327,8 @@ void rti_domain_destroy(rti_domain *D)
     (void)hipStreamSynchronize(D->stream);
     drop_graphs(D);
     if (D->capture) (void)hipStreamDestroy(D->capture);
+    for (auto &x : D->tev)
+        if (x) (void)hipEventDestroy(x);
     if (D->owns_mem && D->mem) (void)hipFree(D->mem);
     delete D;
 }

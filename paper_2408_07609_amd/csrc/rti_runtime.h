@@ -82,6 +82,7 @@ struct rti_domain {
     hipStream_t capture = nullptr;       // private, for graph capture
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of the autotuner, made at create
     void *mem = nullptr;                 // base of the carved memory
     bool owns_mem = false;
     int *ctrl = nullptr;                 // [0..1] active tile counts per step parity, [2] divergence flag

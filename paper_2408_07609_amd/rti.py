@@ -25,6 +25,7 @@ RTI_FLAG_NO_GRAPH, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED, RTI_FLAG_PERSISTENT = 0x
 RTI_MAX_LEVELS = 128
 RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX, RTI_TILE_ROWS_DEFAULT = 4, 64, 12
 RTI_PROBE_CBRT, RTI_PROBE_RECIP, RTI_PROBE_SQRT = 0, 1, 2
+RTI_AUTOTUNE_NOALLOC_MAX_BYTES = 128 << 20
 
 _dptr = ctypes.POINTER(ctypes.c_double)
 
@@ -77,6 +78,8 @@ FUNCTIONS = {
     "rti_domain_set_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rti_domain_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "rti_domain_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
+    "rti_domain_autotune_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                   _dptr]),
     "rti_domain_destroy": (None, [ctypes.c_void_p]),
     "rti_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -242,6 +245,14 @@ def rti_domain_autotune(dom: int, nsteps: int):
     """Returns (tile rows chosen, ms per step at that height)."""
     rows, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
     _check(LIB.rti_domain_autotune(dom, int(nsteps), ctypes.byref(rows), ctypes.byref(ms)))
+    return int(rows.value), float(ms.value)
+
+
+def rti_domain_autotune_noalloc(dom: int, nsteps: int):
+    """rti_domain_autotune staged in the library's static device array (no
+    allocation).  Returns (tile rows chosen, ms per step at that height)."""
+    rows, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(LIB.rti_domain_autotune_noalloc(dom, int(nsteps), ctypes.byref(rows), ctypes.byref(ms)))
     return int(rows.value), float(ms.value)
 
 
@@ -423,6 +434,11 @@ class Domain:
         """Time every candidate tile height from the current state, keep the
         fastest, restore the state.  Returns (rows, ms per step)."""
         return rti_domain_autotune(self._h, nsteps)
+
+    def autotune_noalloc(self, nsteps=20):
+        """autotune without allocating device memory (the snapshot is staged
+        in the library's static array of RTI_AUTOTUNE_NOALLOC_MAX_BYTES)."""
+        return rti_domain_autotune_noalloc(self._h, nsteps)
 
 
 class Batch:
