@@ -76,19 +76,39 @@ def measured_traffic(kernel, workload, cells_per_launch):
 
 
 COPY_PROBE_BYTES = 1 << 30
+MIX_PROBE_DOUBLES = 1 << 26      # 512 MiB per array
 
 
 def copy_probe():
-    """A plain 1 GiB device-to-device copy by torch's copy kernel: rocprofv3's
-    FETCH_SIZE / WRITE_SIZE readings of it give the factor between the
-    counters and real bytes."""
+    """Project-written streams (rti_stream_probe), timed with HIP events on
+    torch's stream: a plain 1 GiB copy (k_stream_copy; rocprofv3's FETCH_SIZE
+    and WRITE_SIZE readings of it give the factor between the counters and
+    real bytes), and the FP64 step's mix of 5 reads and 4 writes per element
+    (k_stream_probe), the practical HBM ceiling for the step's kernels."""
     import torch
+    from paper_2408_07609_amd import rti
+    out = {}
     src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    log(f"copy probe: 3 copies of {COPY_PROBE_BYTES} bytes")
+    ins = [torch.full((MIX_PROBE_DOUBLES,), float(k + 1), dtype=torch.float64, device="cuda:0") for k in range(5)]
+    outs = [torch.empty(MIX_PROBE_DOUBLES, dtype=torch.float64, device="cuda:0") for _ in range(4)]
+    for name, fn, nbytes in (("copy", lambda: rti.stream_probe([src], [dst]), 2 * COPY_PROBE_BYTES),
+                             ("mix_5r4w", lambda: rti.stream_probe(ins, outs), 9 * 8 * MIX_PROBE_DOUBLES)):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(3):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        s = ev0.elapsed_time(ev1) / 3e3
+        out[name] = {"bytes": nbytes, "ms": s * 1e3, "GB_per_s": nbytes / s / 1e9,
+                     "frac_of_peak": nbytes / s / 1e9 / HBM_PEAK_GBS}
+    log(f"stream probes: {out}")
+    del src, dst, ins, outs
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_model():
@@ -379,12 +399,25 @@ def timed_steps(d, steps, torch):
     return wall, ev0.elapsed_time(ev1) / 1e3, all1 - all0, comp1 - comp0
 
 
-def full_run(sc, prec, flags, torch, np):
+def tile_rows(d, args):
+    """The tile height: --tile-rows if given, else the library's autotuner
+    (every candidate height timed from the current state with every tile
+    computed; the state is restored exactly)."""
+    if args.tile_rows:
+        d.set_tile_rows(args.tile_rows)
+        return args.tile_rows
+    rows, ms = d.autotune(8)
+    log(f"autotuned tile rows: {rows} ({ms:.4f} ms per step, every tile computed)")
+    return rows
+
+
+def full_run(sc, prec, flags, torch, np, args):
     """The whole configuration from t = 0 with stationary tiles skipped: the
     graph is captured by untimed steps first, then the state goes back to
     t = 0 (which, like a new domain, computes every tile in the first two
     steps) and all sc.steps steps are timed."""
     d = make_domain(sc, prec, flags)
+    rows = tile_rows(d, args)
     init = [d.get_state(k) for k in range(len(sc.levels))]
     zinit = [d.max_inundation(k) for k in range(len(sc.levels))]
     d.step(2 * GRAPH_STEPS)
@@ -399,7 +432,7 @@ def full_run(sc, prec, flags, torch, np):
     for k in range(len(sc.levels)):
         assert np.all(np.isfinite(d.get_state(k)[0])), "non-finite state after the full run"
     log(f"full run: {wall:.2f} s wall, {ev_s:.2f} s by events, computed fraction {comp / all_:.3f}")
-    return d, dict(steps=sc.steps, simulated_s=sc.steps * sc.dt, wall_s=wall, events_s=ev_s,
+    return d, dict(steps=sc.steps, simulated_s=sc.steps * sc.dt, tile_rows=rows, wall_s=wall, events_s=ev_s,
                    value=sc.cells * sc.steps / wall, unit="cell-updates/s", computed_cell_updates=comp,
                    computed_fraction=comp / all_, active_cell_updates_per_s=comp / wall)
 
@@ -423,8 +456,7 @@ def bench_single(args):
         # every tile computed; warmup (at least one graph's worth, rounded up
         # to whole graphs so the timed window starts on a captured graph)
         d = make_domain(sc, prec, args.flags | RTI_FLAG_NO_ACTIVE)
-        if args.tile_rows:
-            d.set_tile_rows(args.tile_rows)
+        rows = tile_rows(d, args)
         prep = max(args.warmup, GRAPH_STEPS)
         prep = (prep + GRAPH_STEPS - 1) // GRAPH_STEPS * GRAPH_STEPS
         d.step(prep)
@@ -435,7 +467,8 @@ def bench_single(args):
         window = "dense"
         untimed = prep
     else:
-        d, full = full_run(sc, prec, args.flags, torch, np)
+        d, full = full_run(sc, prec, args.flags, torch, np, args)
+        rows = full["tile_rows"]
         wall, ev_s, all_, comp = full["wall_s"], full["events_s"], sc.cells * steps, full["computed_cell_updates"]
         window = "full_run"
         untimed = 2 * GRAPH_STEPS
@@ -452,10 +485,9 @@ def bench_single(args):
     log(f"kernel times (ms/launch): {prof}; cells per launch {units:.0f}")
     d.close()
     del d
-    if args.copy_probe:
-        copy_probe()
+    probes = copy_probe() if args.copy_probe else None
     if dense and not args.no_full_run:
-        dfull, full = full_run(sc, prec, args.flags, torch, np)
+        dfull, full = full_run(sc, prec, args.flags, torch, np, args)
         fprof, fcells = dfull.profile(args.profile_steps)
         full["kernel_ms_at_end"] = fprof
         full["cells_per_launch_at_end"] = fcells
@@ -489,7 +521,8 @@ def bench_single(args):
             "computed_cell_updates": comp,
             "active_cell_updates_per_s": comp / wall,
             "flags": args.flags | (RTI_FLAG_NO_ACTIVE if dense else 0),
-            "tile_rows": args.tile_rows or 12,
+            "tile_rows": rows,
+            "tile_rows_from": "--tile-rows" if args.tile_rows else "autotuner",
         },
         "roofline": {
             "bound": "hbm",
@@ -508,6 +541,8 @@ def bench_single(args):
     }
     if full is not None and dense:
         out["full_run"] = full
+    if probes is not None:
+        out["stream_probes"] = probes
     if prec == RTI_FP32_BULK and not args.no_fp64:
         out["fp32_bulk_error_vs_fp64"] = fp32_error(sc, args.flags, steps if dense else sc.steps, np)
     if not args.no_cpu_baseline:
@@ -557,7 +592,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run the stream probes (1 GiB copy for counter calibration, 5-read/4-write ceiling)")
     ap.add_argument("--persistent", action="store_true", help="c4: persistent grid for the batched kernel")
     ap.add_argument("--no-fp64", action="store_true", help="c4: skip the FP64 comparison run")
     ap.add_argument("--compare-steps", type=int, default=600, help="c4: steps before the FP32-bulk error is taken")

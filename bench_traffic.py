@@ -2,10 +2,10 @@
 """Turn two rocprofv3 counter runs of bench.py into profiles/traffic.json.
 
 Each run is `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) with csv output of
-`bench.py ... --copy-probe --flags 3` (no graph, no tile skipping: every
-launch computes every cell).  FETCH_SIZE and WRITE_SIZE are in KiB per
-dispatch.  The 1 GiB copy kernel in the same run calibrates each counter
-(reading / true bytes); the fused kernel's per-dispatch readings divided by
+`bench.py --steps K ... --copy-probe --flags 1` (dense window: every launch
+computes every cell; no graph).  FETCH_SIZE and WRITE_SIZE are in KiB per
+dispatch.  The project's 1 GiB copy kernel (k_stream_copy) in the same run
+calibrates each counter (reading / true bytes); the fused kernel's per-dispatch readings divided by
 that factor and by the cells of the workload give its HBM bytes per computed
 cell, stored with the kernel source hash so bench.py can tell when they are
 stale.
@@ -51,7 +51,7 @@ def main():
     per = {}
     for which, path, counter in (("fetch", args.fetch_csv, "FETCH_SIZE"), ("write", args.write_csv, "WRITE_SIZE")):
         vals = per_kernel(path, counter)
-        copy = [v for k, vs in vals.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+        copy = [v for k, vs in vals.items() if "k_stream_copy" in k for v in vs]
         big = [v for v in copy if v * 1024 > 0.1 * COPY_PROBE_BYTES]
         if not big:
             sys.exit(f"no copy-probe dispatch in {path}")

@@ -55,7 +55,8 @@ enum {
     RTI_ECFL = -4,         /* Eq. (4) violated on some level */
     RTI_ENEST = -5,        /* nesting rule violated (ratio 3, inclusion, margin) */
     RTI_ESTATE = -6,       /* call not allowed in the domain's current state */
-    RTI_EDIVERGED = -7     /* non-finite water level or flux found (sticky) */
+    RTI_EDIVERGED = -7,    /* non-finite water level or flux found (sticky) */
+    RTI_EINTERNAL = -8     /* an internal device check failed (active-tile list overflow; sticky) */
 };
 
 /* Arithmetic of the step.  RTI_FP64: everything in binary64.  RTI_FP32_BULK:
@@ -135,9 +136,14 @@ int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes);
 int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_bytes,
                       void *hip_stream, rti_domain **out);
 
-/* Parametric initial condition (see rti_source) on every level at t = 0:
- * sea cells (h > 0) take the displacement, land keeps eta = -h, a level below
+/* Parametric initial condition (see rti_source) on every level at t = 0.
+ * The time-integration loop of Sec. IV-A starts from an initial water level
+ * that the fault model outside the loop provides; the paper gives that model
+ * no form, so the instantaneous displacement shapes here are a reading.
+ * Sea cells (h > 0) take the displacement, land keeps eta = -h, a level below
  * the ground is clipped to it; fluxes zero; maxima start at these values.
+ * Evaluated on the device with the device's exp, sin and cos (not correctly
+ * rounded: within a few ulp of any other evaluation).
  * RTI_ESTATE once the domain has stepped (use rti_set_state to restart). */
 int rti_set_source(rti_domain *dom, const rti_source *src);
 
@@ -146,16 +152,25 @@ int rti_set_source(rti_domain *dom, const rti_source *src);
 int rti_set_eta(rti_domain *dom, int32_t level, const double *eta0);
 
 /* Enqueue nsteps time steps on the domain's stream and return (asynchronous).
- * nsteps >= 0. */
+ * One step is one iteration of the loop of Sec. IV-A: continuity (Eq. 1) on
+ * every level, the child-to-parent water level on the footprint rings
+ * (Sec. IV-C), momentum (Eqs. 2-3), the parent-to-child fluxes and the open
+ * or wall sides of the root, and the output maxima; every level advances by
+ * the same dt (Sec. V-A).  FP64 results are bitwise reproducible (every
+ * operation correctly rounded).  nsteps >= 0.  RTI_EDIVERGED if an earlier
+ * synchronising call found the domain diverged. */
 int rti_step(rti_domain *dom, int64_t nsteps);
 
-/* Step until round(t_end / dt) steps have been taken in total, then
- * synchronise and check the state for non-finite values (RTI_EDIVERGED). */
+/* Step until round(t_end / dt) steps have been taken in total (the paper's
+ * forecast is a 6 h run at dt = 0.2 s, Sec. V-A: 108,000 steps), then
+ * synchronise, check every level for non-finite values and read the sticky
+ * device checks (RTI_EDIVERGED, RTI_EINTERNAL as rti_sync). */
 int rti_run(rti_domain *dom, double t_end);
 
-/* Maxima of one level (host out, nx*ny): the highest water level on sea cells
- * (h > 0) and the largest total depth h + eta on land (h <= 0), over every
- * step taken, t = 0 included.  Synchronises. */
+/* Maxima of one level (host out, nx*ny), the outputs the loop of Sec. IV-A
+ * accumulates at the end of each iteration: the highest water level on sea
+ * cells (h > 0) and the largest total depth h + eta, the inundation depth,
+ * on land (h <= 0), over every step taken, t = 0 included.  Synchronises. */
 int rti_max_inundation(rti_domain *dom, int32_t level, double *out);
 
 /* Copy the state of one level to the host (any pointer may be NULL to skip
@@ -172,8 +187,19 @@ int rti_set_max(rti_domain *dom, int32_t level, const double *zmax);
 /* Steps taken since the initial condition. */
 int rti_steps_done(const rti_domain *dom, int64_t *steps);
 
-/* Wait for every step enqueued on the domain's stream. */
+/* Wait for every step enqueued on the domain's stream, then read the
+ * domain's sticky device checks: RTI_EDIVERGED (and the domain is marked
+ * diverged: further steps are refused) once any step wrote a non-finite
+ * water level or flux (the fused kernel checks every value it writes, every
+ * step), RTI_EINTERNAL if an active-tile list ever overflowed (a broken
+ * invariant: each tile is listed at most once per step). */
 int rti_sync(rti_domain *dom);
+
+/* The sticky device checks without failing on them (synchronises):
+ * *bits = RTI_STATUS_DIVERGED | RTI_STATUS_LIST_OVERFLOW as set. */
+#define RTI_STATUS_DIVERGED 0x1u
+#define RTI_STATUS_LIST_OVERFLOW 0x2u
+int rti_device_status(rti_domain *dom, uint32_t *bits);
 
 /* Time the kernels of nsteps steps launched one by one with HIP events on
  * the domain's stream (this advances the state).  ms[k] receives the average
@@ -289,6 +315,16 @@ void rti_batch_destroy(rti_batch *batch);
  * array with n > 0. */
 enum { RTI_PROBE_CBRT = 0, RTI_PROBE_RECIP = 1, RTI_PROBE_SQRT = 2 };
 int rti_math_probe(int32_t op, const double *x, double *y, int64_t n, void *hip_stream);
+
+/* Diagnostic: the HBM rate a plain stream reaches on this GPU, as the
+ * practical ceiling for the step's kernels (which move 5 reads and 4 writes
+ * of 8 bytes per cell in FP64).  out[j][i] = (j + 1) * sum_k in[k][i] over n
+ * doubles; in: `reads` (1..8) device arrays, out: `writes` (0..8) device
+ * arrays, none overlapping; host arrays of the device pointers.  Enqueued on
+ * hip_stream (borrowed); returns without waiting.  RTI_EINVAL on a bad count,
+ * n < 0 or a NULL pointer. */
+int rti_stream_probe(const double *const *in, int32_t reads, double *const *out, int32_t writes, int64_t n,
+                     void *hip_stream);
 
 const char *rti_last_error(void);
 const char *rti_strerror(int code);

@@ -37,6 +37,7 @@ struct rti_batch {
     unsigned long long cells_done = 0;   // computed cells carried over when the tables are rebuilt
     size_t nslot = 0;                    // computed-cell slots of the current tables
     int64_t cell_updates_all = 0;        // every member's cells times the steps it took in the batch
+    bool overflowed = false;             // the global list's overflow flag was seen set (sticky)
 };
 
 namespace {
@@ -82,9 +83,22 @@ int sum_cells(rti_batch *B, unsigned long long *out)
     return RTI_OK;
 }
 
+// The global list's overflow flag into the sticky host flag (synchronises);
+// the tables' flag is cleared when they are rebuilt.
+int read_overflow(rti_batch *B)
+{
+    if (!B->dev.status) return RTI_OK;
+    int st = 0;
+    HIP_TRY(hipMemcpyAsync(&st, B->dev.status + 1, sizeof st, hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    if (st) B->overflowed = true;
+    return RTI_OK;
+}
+
 int build_tables(rti_batch *B)
 {
     HIP_TRY(hipStreamSynchronize(B->stream));
+    if (int rc = read_overflow(B)) return rc;
     if (B->mem) {   // carry the computed-cells total over to the new tables
         unsigned long long t = 0;
         int rc = sum_cells(B, &t);
@@ -142,7 +156,7 @@ int build_tables(rti_batch *B)
     if (ntiles)
         HIP_TRY(hipMemcpyAsync(p + o_tdom, B->tdom.data(), sizeof(uint16_t) * ntiles, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_par, par.data(), (size_t)n, hipMemcpyHostToDevice, B->stream));
-    HIP_TRY(hipMemsetAsync(p + o_count, 0, 16, B->stream));                  // list counters
+    HIP_TRY(hipMemsetAsync(p + o_count, 0, 16, B->stream));                  // list counters, status
     HIP_TRY(hipMemsetAsync(p + o_cells, 0, sizeof(unsigned long long) * nslot, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_cells, &B->cells_done, sizeof B->cells_done, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(p + o_rbase, rbase.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, B->stream));
@@ -157,6 +171,7 @@ int build_tables(rti_batch *B)
     bd.list = reinterpret_cast<int32_t *>(p + o_list);
     bd.lmeta = reinterpret_cast<int32_t *>(p + o_lmeta);
     bd.count = reinterpret_cast<int32_t *>(p + o_count);
+    bd.status = bd.count + 2;
     bd.cells_done = reinterpret_cast<unsigned long long *>(p + o_cells);
     bd.rbase = reinterpret_cast<const int32_t *>(p + o_rbase);
     bd.rdom = reinterpret_cast<const uint16_t *>(p + o_rdom);
@@ -356,6 +371,10 @@ int rti_batch_sync(rti_batch *B)
 {
     if (!B) return fail(RTI_EINVAL, "batch is NULL");
     HIP_TRY(hipStreamSynchronize(B->stream));
+    if (int rc = read_overflow(B)) return rc;
+    if (B->overflowed) return fail(RTI_EINTERNAL, "the batch's active-tile list overflowed on the device");
+    for (rti_domain *D : B->members)
+        if (int rc = check_status(D)) return rc;
     return RTI_OK;
 }
 

@@ -97,8 +97,9 @@ __device__ __forceinline__ bool midpoint_cube_below(double lo, double hi, double
     return (w2 < b2) || (w2 == b2 && w1 < b1);
 }
 
-// Cube root of a positive normal double, correctly rounded (the double
-// nearest to the real root).  x = a 2^(3q) with a in [0.5, 4).  An estimate
+// Cube root, correctly rounded (the double nearest to the real root), on the
+// reduced range: x = a 2^(3q) with a in [0.5, 4), so that the root of a and
+// its neighbours lie in [0.5, 2) as midpoint_cube_below needs.  An estimate
 // z of a^(-1/3) from binary32 log2/exp2 (relative error about 2^-22) gets a
 // correction of second order: with e = 1 - a z^3, a^(-1/3) = z (1 - e)^(-1/3)
 // = z (1 + e/3 + 2e^2/9 + O(e^3)), leaving an error near 2^-52.  y = a z^2
@@ -108,8 +109,8 @@ __device__ __forceinline__ bool midpoint_cube_below(double lo, double hi, double
 // s = y + d rounded is the nearest double unless the root lies within 2^-21
 // ulp of the midpoint between s and its neighbour on that side (err, the
 // exact rounding error of y + d, says how close); that case is settled by
-// the exact test midpoint_cube_below.
-__device__ __forceinline__ double cbrt_rn(double x)
+// the exact test.  Any positive normal x.
+__device__ __forceinline__ double cbrt_rn_reduced(double x)
 {
     const int ex = __builtin_amdgcn_frexp_exp(x);                    // x = m 2^ex, m in [0.5, 1)
     const int q = (ex + 1023) / 3 - 341;                             // floor(ex / 3)
@@ -133,6 +134,38 @@ __device__ __forceinline__ double cbrt_rn(double x)
         r = (err > 0.0) ? (above_mid ? nb : s) : (above_mid ? s : nb);
     }
     return __builtin_amdgcn_ldexp(r, q);
+}
+
+// The cube root of the friction term: the same steps without the range
+// reduction for x in [2^-120, 2^120] (where the binary32 estimate and the
+// exact products neither overflow nor underflow, and the relative error
+// bounds above do not depend on the scale), falling back to the reduced
+// form outside that range and whenever the root lies too near a midpoint
+// for the fast decision.  Correctly rounded for every positive normal x.
+__device__ __forceinline__ double cbrt_rn(double x)
+{
+    double r;
+    bool slow = !(x >= 0x1p-120 && x <= 0x1p120);
+    {
+        const float xf = (float)(slow ? 1.0 : x);
+        double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf(xf));
+        const double xs = slow ? 1.0 : x;
+        const double e = fma(-xs, (z * z) * z, 1.0);
+        z = fma(z * e, fma(e, 2.0 / 9.0, 1.0 / 3.0), z);
+        const double y = (xs * z) * z;
+        const double p = y * y, pl = fma(y, y, -p);
+        const double t = p * y, tl = fma(p, y, -t);
+        const double res = ((xs - t) - tl) - pl * y;
+        const double d = res * ((z * z) * (1.0 / 3.0));
+        const double s = y + d;
+        const double err = d - (s - y);
+        const long long bits = __double_as_longlong(s);
+        const double nb = __longlong_as_double(err > 0.0 ? bits + 1 : bits - 1);
+        slow = slow || (fabs(err) > fabs(0.5 * (nb - s)) * (1.0 - 0x1p-20));
+        r = s;
+    }
+    if (slow) r = cbrt_rn_reduced(x);
+    return r;
 }
 
 // Reciprocal of a face depth: IEEE division in FP64.

@@ -332,6 +332,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
         w[k].R = ld_ring(t0 + k);
     }
     bool quiet = true;
+    bool bad = false;            // a non-finite value written (the divergence watchdog)
 
     auto do_row = [&](auto kc, int t) {
         constexpr int K = decltype(kc)::value;
@@ -413,6 +414,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
                 }
                 // the fluxes this tile writes left unchanged?
                 quiet = quiet && (!wx || same_bits(Mnew, xp.f)) && (!wy || same_bits(Nnew, yp.f));
+                bad = bad || (wx && !isfinite(Mnew)) || (wy && !isfinite(Nnew)) || (col_cell && rr < ny && !isfinite(p.e1));
                 if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew, cmask);
             }
         }
@@ -450,6 +452,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
     // Stationarity history of the tile: bit1 <- bit0, bit0 <- this step left
     // every value the tile writes (water levels, fluxes) bitwise unchanged.
     const bool all_quiet = __all(quiet ? 1 : 0);
+    if (__any(bad ? 1 : 0) && lane == 0) atomicOr(&d.status[0], 1);   // sticky: RTI_EDIVERGED on the host
     if (lane == 0) {
         const uint8_t old = d.tflag[g];
         const uint8_t nw = (info & TI_PINNED) ? 0 : (uint8_t)(((old & 1u) << 1) | (all_quiet ? 1u : 0u));
@@ -573,7 +576,7 @@ __device__ __forceinline__ int tile_active(const DomainDev &d, int g, int all_ac
 // The counter of the other parity, read by nobody during this step, is reset
 // for the next one, so no memset is needed between steps.
 __device__ __forceinline__ void append_active(int a, int id, int meta, int tb, int *count_b, int *count_other, int *list,
-                                              int *lmeta, int cap)
+                                              int *lmeta, int cap, int *overflow)
 {
     __shared__ int wsum[4];
     __shared__ int base;
@@ -595,15 +598,17 @@ __device__ __forceinline__ void append_active(int a, int id, int meta, int tb, i
     if (tid == 0) base = total ? atomicAdd(count_b, total) : 0;
     if (tb == 0 && tid == 0) *count_other = 0;
     __syncthreads();
-    // A list holds at most cap (= tiles) entries; the bound also keeps the
-    // writes inside the list if the launch were ever executed twice for one
-    // step (the count would then pass cap; the first cap entries, which
-    // include every active tile, are what the fused kernel reads).
+    // A list holds at most cap (= tiles) entries: each tile is listed at most
+    // once per step, so a position at or beyond cap means the counter was not
+    // reset for this step.  The entry is then dropped (the writes stay inside
+    // the list) and the sticky overflow flag raised, which the host reports
+    // as RTI_EINTERNAL at the next synchronising call.
     const int pos = base + before + incl - 1;
     if (a && pos < cap) {
         list[pos] = id;
         lmeta[pos] = meta;
     }
+    if (a && pos >= cap) atomicOr(overflow, 1);
 }
 
 // Sum of c over the workgroup added to slot `slot` of part (no atomics: each
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int a = (g < d.ntiles) ? tile_active(d, g, all_active) : 0;
     const int l = (g < d.ntiles) ? level_of_tile(d, g) : 0;
     add_cells(a ? d.tcells[g] : 0, d.cells_done, tb);
-    append_active(a, g, l, tb, &d.count[b], &d.count[b ^ 1], d.list, d.lmeta, d.ntiles);
+    append_active(a, g, l, tb, &d.count[b], &d.count[b ^ 1], d.list, d.lmeta, d.ntiles, &d.status[1]);
 }
 
 // The same over a batch's global tables: each member's own flags decide, and
@@ -672,7 +677,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         meta = (level_of_tile(d, G - bd.base[m]) << 16) | m;
     }
     add_cells(c, bd.cells_done, tb);
-    append_active(a, G, meta, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list, bd.lmeta, bd.ntiles);
+    append_active(a, G, meta, tb, &bd.count[flip], &bd.count[flip ^ 1], bd.list, bd.lmeta, bd.ntiles, &bd.status[1]);
 }
 
 }  // namespace

@@ -366,7 +366,8 @@ int carve(rti_domain *D)
     D->tcells = reinterpret_cast<int32_t *>(take(align_up(nt * 4, kAlign)));
     D->dev.tcells = D->tcells;
     D->ctrl = reinterpret_cast<int *>(take(kAlign));
-    D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity, ctrl[2] divergence flag
+    D->dev.count = D->ctrl;         // ctrl[0..1]: active tiles per step parity
+    D->dev.status = D->ctrl + 2;    // ctrl[2]: non-finite value written, ctrl[3]: list overflow (both sticky)
     D->dev.cells_done = reinterpret_cast<unsigned long long *>(
         take(align_up(sizeof(unsigned long long) * ((nt + 255) / 256), kAlign)));
     const size_t nl = D->plan.lv.size();
@@ -440,6 +441,21 @@ int check_level(const rti_domain *D, int level)
 int rti_rt::forget_quiet(rti_domain *D)
 {
     HIP_TRY(hipMemsetAsync(D->dev.tflag, 0, (size_t)D->plan.ntiles, D->stream));
+    return RTI_OK;
+}
+
+// The sticky device checks, read after the stream has drained: a list
+// overflow is an internal error; a non-finite value marks the domain diverged.
+int rti_rt::check_status(rti_domain *D)
+{
+    int st[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(st, D->dev.status, sizeof st, hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    if (st[1]) return fail(RTI_EINTERNAL, "an active-tile list overflowed on the device");
+    if (st[0]) {
+        D->diverged = true;
+        return fail(RTI_EDIVERGED, "non-finite water level or flux after %lld steps", (long long)D->steps);
+    }
     return RTI_OK;
 }
 
@@ -674,6 +690,7 @@ const char *rti_strerror(int code)
     case RTI_ENEST: return "nesting rule violated";
     case RTI_ESTATE: return "call not allowed in this state";
     case RTI_EDIVERGED: return "simulation diverged";
+    case RTI_EINTERNAL: return "internal device check failed";
     default: return "unknown error";
     }
 }
@@ -944,10 +961,39 @@ int rti_math_probe(int32_t op, const double *x, double *y, int64_t n, void *hip_
     return RTI_OK;
 }
 
+int rti_stream_probe(const double *const *in, int32_t reads, double *const *out, int32_t writes, int64_t n,
+                     void *hip_stream)
+{
+    if (reads < 1 || reads > 8 || writes < 0 || writes > 8) return fail(RTI_EINVAL, "reads %d / writes %d", reads, writes);
+    if (n < 0) return fail(RTI_EINVAL, "n %lld < 0", (long long)n);
+    if (!in || (writes > 0 && !out)) return fail(RTI_EINVAL, "NULL array list");
+    for (int k = 0; k < reads; ++k)
+        if (!in[k]) return fail(RTI_EINVAL, "input %d is NULL", k);
+    for (int k = 0; k < writes; ++k)
+        if (!out[k]) return fail(RTI_EINVAL, "output %d is NULL", k);
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t want = (n + 255) / 256;
+    const int grid = (int)std::min<int64_t>(want, (int64_t)cus * 16);
+    HIP_TRY(launch_stream_probe(in, reads, out, writes, n, std::max(grid, 1), static_cast<hipStream_t>(hip_stream)));
+    return RTI_OK;
+}
+
 int rti_sync(rti_domain *D)
 {
     if (!D) return fail(RTI_EINVAL, "domain is NULL");
     HIP_TRY(hipStreamSynchronize(D->stream));
+    return check_status(D);
+}
+
+int rti_device_status(rti_domain *D, uint32_t *bits)
+{
+    if (!D || !bits) return fail(RTI_EINVAL, "NULL argument");
+    int st[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(st, D->dev.status, sizeof st, hipMemcpyDeviceToHost, D->stream));
+    HIP_TRY(hipStreamSynchronize(D->stream));
+    *bits = (st[0] ? RTI_STATUS_DIVERGED : 0u) | (st[1] ? RTI_STATUS_LIST_OVERFLOW : 0u);
     return RTI_OK;
 }
 
@@ -961,16 +1007,11 @@ int rti_run(rti_domain *D, double t_end)
         int rc = rti_step(D, target - D->steps);
         if (rc) return rc;
     }
-    HIP_TRY(launch_zero_int(D->ctrl + 2, 1, D->stream));
-    HIP_TRY(launch_finite_check(D->dev, D->cur, D->ctrl + 2, D->stream));
-    int flag = 0;
-    HIP_TRY(hipMemcpyAsync(&flag, D->ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, D->stream));
+    // the fused kernel's watchdog saw every value it wrote; this whole-level
+    // pass also covers the per-phase kernels and values set from the host
+    HIP_TRY(launch_finite_check(D->dev, D->cur, D->dev.status, D->stream));
     HIP_TRY(hipStreamSynchronize(D->stream));
-    if (flag) {
-        D->diverged = true;
-        return fail(RTI_EDIVERGED, "non-finite water level or flux after %lld steps", (long long)D->steps);
-    }
-    return RTI_OK;
+    return check_status(D);
 }
 
 int rti_max_inundation(rti_domain *D, int32_t level, double *out)

@@ -102,6 +102,8 @@ struct DomainDev {
     int32_t *list;                         // ntiles: active tiles of the current step
     int32_t *lmeta;                        // ntiles: level of each listed tile (written with the list)
     int32_t *count;                        // [b] number of active tiles of a step reading buffer b
+    int32_t *status;                       // sticky device checks: [0] a non-finite level or flux was
+                                           // written, [1] an active-tile list would have overflowed
     const int32_t *tcells;                 // ntiles: cells of the level inside each tile
     unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles, summed over the steps
     const LevelDev *lv;                    // nlev levels (blocks of a resolution): device table
@@ -141,6 +143,7 @@ struct BatchDev {
     int32_t *list;                         // ntiles: active global tiles of the current step
     int32_t *lmeta;                        // ntiles: level << 16 | member of each listed tile (written with the list)
     int32_t *count;                        // [flip]
+    int32_t *status;                       // [1]: the global active-tile list would have overflowed (sticky)
     unsigned long long *cells_done;        // per active-list workgroup: cells of the computed tiles of all members
     int32_t nring;                         // ring cells of all members
     const int32_t *rbase;                  // n + 1: member m's ring cells are global ring cells rbase[m] .. rbase[m+1]-1
@@ -175,3 +178,5 @@ hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
 hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s);
 hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s);
 hipError_t launch_probe_math(int op, const double *x, double *y, int64_t n, hipStream_t s);
+hipError_t launch_stream_probe(const double *const *in, int reads, double *const *out, int writes, int64_t n,
+                               int grid, hipStream_t s);

@@ -303,7 +303,49 @@ __global__ __launch_bounds__(256) void k_probe_math(int op, const double *x, dou
     y[k] = (op == 0) ? cbrt_rn(v) : (op == 1) ? inv_depth(v) : sqrt(v);
 }
 
+// A plain stream over n doubles: `reads` input arrays and `writes` output
+// arrays, out_j[i] = (j + 1) * (sum of the inputs at i), one element per
+// lane per array (the access width of the step's kernels), a grid-stride
+// loop over a fixed grid.  It measures the HBM rate that a kernel moving the
+// step's mix of reads and writes can reach on this GPU; one read and one
+// write is a plain copy (k_stream_copy).
+struct StreamArgs {
+    const double *in[8];
+    double *out[8];
+};
+
+__global__ __launch_bounds__(256) void k_stream_copy(const double *in, double *out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(&in[i]), &out[i]);
+}
+
+__global__ __launch_bounds__(256) void k_stream_probe(StreamArgs a, int reads, int writes, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+        for (int k = 0; k < reads; ++k) s += __builtin_nontemporal_load(&a.in[k][i]);
+        for (int k = 0; k < writes; ++k) __builtin_nontemporal_store(s * (double)(k + 1), &a.out[k][i]);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_stream_probe(const double *const *in, int reads, double *const *out, int writes, int64_t n,
+                               int grid, hipStream_t s)
+{
+    StreamArgs a{};
+    for (int k = 0; k < reads; ++k) a.in[k] = in[k];
+    for (int k = 0; k < writes; ++k) a.out[k] = out[k];
+    if (n <= 0) return hipSuccess;
+    if (reads == 1 && writes == 1)       // a plain copy (a kernel of its own: it calibrates the HBM counters)
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, s, in[0], out[0], n);
+    else
+        hipLaunchKernelGGL(k_stream_probe, dim3(grid), dim3(256), 0, s, a, reads, writes, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_probe_math(int op, const double *x, double *y, int64_t n, hipStream_t s)
 {

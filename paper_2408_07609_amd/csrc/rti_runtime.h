@@ -108,6 +108,9 @@ struct rti_domain {
 namespace rti_rt {
 // Used by the batch runtime.
 int forget_quiet(rti_domain *D);
+// The sticky device checks (after the stream drained): RTI_EINTERNAL on a list
+// overflow, RTI_EDIVERGED (and the domain marked diverged) on a non-finite value.
+int check_status(rti_domain *D);
 // Zero both active-tile counters.  A step's list is appended at its parity's
 // counter, which the step before resets; whenever a domain's parity moves
 // without its own steps (batch steps, autotune restore) the counters are

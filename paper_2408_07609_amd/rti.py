@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "librti.so")
 
 RTI_OK, RTI_EINVAL, RTI_ENOMEM, RTI_EHIP, RTI_ECFL, RTI_ENEST, RTI_ESTATE, RTI_EDIVERGED = 0, -1, -2, -3, -4, -5, -6, -7
+RTI_EINTERNAL = -8
+RTI_STATUS_DIVERGED, RTI_STATUS_LIST_OVERFLOW = 0x1, 0x2
 RTI_FP64, RTI_FP32_BULK = 0, 1
 RTI_BC_OPEN, RTI_BC_WALL = 0, 1
 RTI_GAUSS, RTI_COS2_ELLIPSE = 0, 1
@@ -68,6 +70,7 @@ FUNCTIONS = {
     "rti_set_max": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dptr]),
     "rti_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rti_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "rti_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "rti_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dptr, ctypes.POINTER(ctypes.c_char_p),
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
     "rti_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -92,6 +95,8 @@ FUNCTIONS = {
     "rti_batch_destroy": (None, [ctypes.c_void_p]),
     "rti_math_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p]),
+    "rti_stream_probe": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]),
     "rti_last_error": (ctypes.c_char_p, []),
     "rti_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -143,6 +148,19 @@ def rti_domain_create(desc: rti_domain_desc, arena_ptr: int | None, arena_bytes:
 
 def rti_math_probe(op: int, x_ptr: int, y_ptr: int, n: int, stream_ptr: int | None):
     _check(LIB.rti_math_probe(op, x_ptr, y_ptr, n, stream_ptr))
+
+
+def stream_probe(inputs, outputs):
+    """rti_stream_probe over float64 device tensors of equal size, on torch's
+    current stream."""
+    import torch
+    n = inputs[0].numel()
+    for t in list(inputs) + list(outputs):
+        if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+            raise ValueError("stream_probe takes contiguous float64 device tensors of one size")
+    ins = (ctypes.c_void_p * len(inputs))(*[t.data_ptr() for t in inputs])
+    outs = (ctypes.c_void_p * max(1, len(outputs)))(*[t.data_ptr() for t in outputs])
+    _check(LIB.rti_stream_probe(ins, len(inputs), outs, len(outputs), n, torch.cuda.current_stream().cuda_stream))
 
 
 def math_probe(op: int, x):
@@ -246,6 +264,12 @@ def rti_domain_autotune(dom: int, nsteps: int):
     rows, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
     _check(LIB.rti_domain_autotune(dom, int(nsteps), ctypes.byref(rows), ctypes.byref(ms)))
     return int(rows.value), float(ms.value)
+
+
+def rti_device_status(dom: int) -> int:
+    bits = ctypes.c_uint32(0)
+    _check(LIB.rti_device_status(dom, ctypes.byref(bits)))
+    return int(bits.value)
 
 
 def rti_domain_autotune_noalloc(dom: int, nsteps: int):
@@ -398,11 +422,22 @@ class Domain:
     def steps(self):
         return rti_steps_done(self._h)
 
+    def device_status(self):
+        """The sticky device checks (RTI_STATUS_* bits); synchronises."""
+        return rti_device_status(self._h)
+
+    def _no_overflow(self):
+        # an overflowed active-tile list breaks an invariant of the library:
+        # every read of results checks for it
+        if self.device_status() & RTI_STATUS_LIST_OVERFLOW:
+            raise RtiError(RTI_EINTERNAL, "an active-tile list overflowed on the device")
+
     # -- results
     def get_state(self, level):
         nx, ny = self.levels[level]["nx"], self.levels[level]["ny"]
         e, M, N = np.empty((ny, nx)), np.empty((ny, nx + 1)), np.empty((ny + 1, nx))
         rti_get_state(self._h, level, e, M, N)
+        self._no_overflow()
         return e, M, N
 
     def max_inundation(self, level):

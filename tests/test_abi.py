@@ -32,6 +32,7 @@ def test_exports_every_declared_symbol():
 def test_strerror():
     assert rti.rti_strerror(rti.RTI_ECFL) == "CFL condition violated"
     assert rti.rti_strerror(rti.RTI_ENEST) == "nesting rule violated"
+    assert rti.rti_strerror(rti.RTI_EINTERNAL) == "internal device check failed"
     assert rti.rti_strerror(12345) == "unknown error"
 
 

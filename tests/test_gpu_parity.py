@@ -240,6 +240,42 @@ def test_errors_on_gpu():
     assert ei.value.code == RTI_EDIVERGED
 
 
+def test_divergence_watchdog_in_the_step():
+    """The fused kernel checks every value it writes: a non-finite level set
+    from the host is caught by rti_sync after plain rti_step calls (graphs of
+    20 steps), the flag is sticky, further steps are refused, and a batch
+    reports its diverged member at rti_batch_sync."""
+    from paper_2408_07609_amd import RTI_EDIVERGED, RTI_STATUS_DIVERGED, Batch, RtiError
+    sc = scenarios.small_nested(seed=7, nlev=3)
+    d = gpu_domain(sc)
+    d.set_source(*sc.source.astuple())
+    d.step(40)
+    d.sync()
+    assert d.device_status() == 0
+    e, M, N = d.get_state(2)
+    e[4, 7] = np.inf
+    d.set_state(2, e, M, N)
+    d.step(40)
+    with pytest.raises(RtiError) as ei:
+        d.sync()
+    assert ei.value.code == RTI_EDIVERGED
+    assert d.device_status() & RTI_STATUS_DIVERGED
+    with pytest.raises(RtiError) as ei:
+        d.step(1)
+    assert ei.value.code == RTI_EDIVERGED
+    a, b = gpu_domain(sc), gpu_domain(scenarios.small_nested(seed=5, nlev=1, base=(150, 40)))
+    a.set_source(*sc.source.astuple())
+    e, M, N = a.get_state(0)
+    M[3, 9] = np.nan
+    a.set_state(0, e, M, N)
+    with Batch([a, b]) as bt:
+        bt.step(20)
+        with pytest.raises(RtiError) as ei:
+            bt.sync()
+        assert ei.value.code == RTI_EDIVERGED
+    assert b.device_status() == 0
+
+
 def test_fused_phased_and_unskipped_agree_bitwise():
     """The fused tile kernel, the per-phase kernels and the fused kernel with
     tile skipping off produce identical bits."""
