@@ -49,7 +49,8 @@ def test_traffic_summary(tmp_path):
         with open(path, "w") as f:
             f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
             for d in range(3):
-                f.write(f"{d},void (anonymous namespace)::k_stream_copy(double const*, double*, long),{counter},{kib * copy_factor}\n")
+                f.write(f'{d},"void (anonymous namespace)::k_stream_copy(double const*, double*, long)",'
+                        f'{counter},{kib * copy_factor}\n')
             for d in range(3, 7):
                 f.write(f"{d},\"(anonymous namespace)::k_fused(DomainDev, int)\",{counter},{fused_kib}\n")
     write(tmp_path / "f.csv", "FETCH_SIZE", 1.25, 1000.0)
