@@ -58,12 +58,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, cells_per_launch):
+def measured_traffic(kernel, workload, cells_per_launch, tile_rows=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (profiles/traffic.json, written by bench_traffic.py): the measured bytes
     per computed cell of this kernel on this workload, times the cells one
     launch computes here.  None when the counters were taken on another
-    kernel source or workload."""
+    kernel source, workload or tile height."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -71,6 +71,8 @@ def measured_traffic(kernel, workload, cells_per_launch):
         t = json.load(f)
     e = t.get(kernel)
     if not e or e.get("source_hash") != source_hash() or e.get("workload") != workload:
+        return None
+    if tile_rows is not None and e.get("tile_rows") not in (None, tile_rows):
         return None
     return e["bytes_per_cell"] * cells_per_launch
 
@@ -531,7 +533,7 @@ def bench_single(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom + ("" if prec == RTI_FP64 else "_fp32bulk"), sc.name, units)
+            "traffic": measured_traffic(dom + ("" if prec == RTI_FP64 else "_fp32bulk"), sc.name, units, rows)
             if dense else None,
             "bytes_per_cell": bpc[dom],
             "cells_per_launch": units,

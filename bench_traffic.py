@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--workload", required=True)
     ap.add_argument("--kernel", default="k_fused", help="substring of the kernel name")
     ap.add_argument("--key", default=None, help="entry name in the json (default: --kernel)")
+    ap.add_argument("--tile-rows", type=int, default=None, help="tile height of the counted runs")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     out = {}
@@ -68,6 +69,7 @@ def main():
         "copy_factor_write": factors["write"],
         "cells": args.cells,
         "workload": args.workload,
+        "tile_rows": args.tile_rows,
         "source_hash": source_hash(),
     }
     path = args.out
