@@ -328,16 +328,20 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """Forecast serving (C5): Poisson arrivals of requests on six nested
-    sites of 1 M to 47 M cells, admitted by device footprint into one running
-    batch (continuous batching), the clock and the 1-6 h durations compressed
-    by --time-scale.  Runs the same request stream in FP32-bulk and in FP64
-    (unless --precision picks one)."""
+    """Forecast serving (C5): Poisson arrivals (2 per minute) of requests on
+    six nested sites of 1 M to 47 M cells, 1-6 h forecasts, admitted by
+    device footprint into one running batch (continuous batching); with
+    --time-scale s the clock and the durations are both divided by s (1, the
+    default, is the stated configuration).  Runs the same request stream in
+    FP32-bulk and in FP64 (unless --precision picks one) and reports p50/p99
+    time to forecast, concurrency, and the cost model's predictions."""
     import torch
 
     import scenarios
     from paper_2408_07609_amd import RTI_FP32_BULK, RTI_FP64
-    from paper_2408_07609_amd.serve import ForecastServer, Request, percentiles
+    import numpy as np
+
+    from paper_2408_07609_amd.serve import ForecastServer, Request, fit_cost_model, percentiles, predict
 
     sites = scenarios.c5_sites()
     stream = scenarios.c5_requests(sites, count=args.requests, time_scale=args.time_scale)
@@ -351,14 +355,28 @@ def bench_serve(args):
     order = [args.precision] if "--precision" in sys.argv else ["fp32-bulk", "fp64"]
     for name in order:
         srv = ForecastServer(budget, precs[name], chunk_steps=args.chunk)
-        res = srv.run(reqs, log=log if args.verbose else None)
+        res = srv.run(reqs, log=log)
         srv.close()
         q = percentiles(res)
+        # the cost model: step time = a * computed cells + b, fitted on the run's chunks; then the
+        # whole stream replayed through the server's policy with that model
+        a, b = fit_cost_model(srv.chunks)
+        frac = sum(c[3] for c in srv.chunks) / max(1, sum(c[0] * c[2] for c in srv.chunks))
+        pred = predict(reqs, a, b, frac, budget, precs[name], args.chunk)
+        rel = [abs(pred[r.rid] - r.time_to_forecast) / r.time_to_forecast for r in res]
+        qp = np.percentile([pred[r.rid] for r in res], [50, 99])
         runs[name] = {"p50_time_to_forecast_s": q["p50"], "p99_time_to_forecast_s": q["p99"],
                       "cell_updates_per_s": srv.cell_updates / srv.makespan, "makespan_s": srv.makespan,
                       "cell_updates": srv.cell_updates, "peak_concurrent": srv.peak_members,
-                      "peak_gib": srv.peak_bytes / 2**30}
-        log(f"{name}: {runs[name]}")
+                      "mean_concurrent": float(sum(r.time_to_forecast for r in res) / srv.makespan),
+                      "peak_gib": srv.peak_bytes / 2**30, "computed_fraction": frac,
+                      "cost_model": {"a_s_per_computed_cell": a, "b_s_per_step": b,
+                                     "predicted_p50_s": float(qp[0]), "predicted_p99_s": float(qp[1]),
+                                     "median_rel_error": float(np.median(rel)), "max_rel_error": float(max(rel))},
+                      "requests": [{"rid": r.rid, "cells": r.cells, "steps": r.steps, "arrival_s": r.arrival,
+                                    "time_to_forecast_s": r.time_to_forecast, "predicted_s": pred[r.rid]}
+                                   for r in sorted(res, key=lambda r: r.rid)]}
+        log(f"{name}: " + json.dumps({k: v for k, v in runs[name].items() if k != "requests"}))
     first = runs[order[0]]
     out = {
         "metric": "cell-updates/s",
@@ -600,7 +618,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="c4: skip the FP64 comparison run")
     ap.add_argument("--compare-steps", type=int, default=600, help="c4: steps before the FP32-bulk error is taken")
     ap.add_argument("--requests", type=int, default=24, help="c5: forecast requests")
-    ap.add_argument("--time-scale", type=float, default=30.0, help="c5: compression of arrivals and durations")
+    ap.add_argument("--time-scale", type=float, default=1.0,
+                    help="c5: compression of arrivals and durations (1: the stated 2 requests/min and 1-6 h)")
     ap.add_argument("--chunk", type=int, default=200, help="c5: batch steps between admission points")
     ap.add_argument("--hbm-gib", type=float, default=0.0, help="c5: HBM budget (default 80%% of free memory)")
     ap.add_argument("--no-full-run", action="store_true", help="dense window only: skip the whole-run measurement")

@@ -31,6 +31,7 @@ class Request:
     source: tuple                # rti_source fields (xc, yc, a, b, theta, amp, shape)
     steps: int                   # time steps to simulate
     arrival: float               # seconds after the server starts
+    initial: list | None = None  # optional raw initial water level per level (instead of the source)
 
 
 @dataclasses.dataclass
@@ -87,13 +88,18 @@ class ForecastServer:
         self.peak_members = 0
         self.peak_bytes = 0
         self.cell_updates = 0
+        self.chunks = []        # (steps, seconds, cells of the members, cells computed) per chunk
 
     def _admit(self, req: Request, now: float):
         from .rti import Domain
         s = req.site
         d = Domain(s.levels, s.dx0, s.dt, g=s.g, manning_n=s.manning_n, dry_eps=s.dry_eps, bc=s.bc, x0=s.x0, y0=s.y0,
                    flags=self.flags, device=self.device, stream=self.stage, precision=self.precision)
-        d.set_source(*req.source)
+        if req.initial is not None:
+            for k, eta0 in enumerate(req.initial):
+                d.set_eta(k, eta0)
+        else:
+            d.set_source(*req.source)
         self.batch.add(d)       # waits for the staging stream only; the running chunk goes on
         return d
 
@@ -114,9 +120,12 @@ class ForecastServer:
             chunk = []
             if active:
                 n = min(self.chunk, min(a[2] for a in active.values()))
+                c_all0, c_comp0 = self.batch.cell_updates()
+                t_chunk = clock()
                 self.batch.step(n)
                 chunk = list(active)
-                self.cell_updates += n * sum(a[0].site.cells for a in active.values())
+                cells = sum(a[0].site.cells for a in active.values())
+                self.cell_updates += n * cells
             # 2. while it runs: take in arrivals, admit in arrival order while the head fits
             now = clock() - t0
             while pending and pending[0].arrival <= now:
@@ -141,6 +150,8 @@ class ForecastServer:
                 continue
             # 3. the chunk is done: retire the requests that reached their step count
             self.batch.sync()
+            c_all1, c_comp1 = self.batch.cell_updates()
+            self.chunks.append((n, clock() - t_chunk, cells, c_comp1 - c_comp0))
             for rid in chunk:
                 active[rid][2] -= n
             for rid in [rid for rid in chunk if active[rid][2] == 0]:
@@ -162,6 +173,53 @@ class ForecastServer:
         if self.batch is not None:
             self.batch.close()
             self.batch = None
+
+
+def fit_cost_model(chunks):
+    """The time of one batch step as a * (cells computed in the step) + b
+    (least squares over the chunks of a serving run; the per-launch term b
+    holds the launch and listing overhead).  The analogue of the paper's
+    per-block cost model (Sec. IV-D, Eq. 5: a cost per cell plus a cost per
+    block), with the batch's one launch per step in place of a block."""
+    A = np.array([[c[3] / c[0], 1.0] for c in chunks if c[0] > 0])
+    y = np.array([c[1] / c[0] for c in chunks if c[0] > 0])
+    w = np.sqrt(np.array([c[0] for c in chunks if c[0] > 0], dtype=np.float64))   # long chunks count more
+    (a, b), *_ = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)
+    return float(a), float(b)
+
+
+def predict(requests, a, b, computed_fraction, hbm_budget, precision, chunk_steps, flags=0):
+    """Times to forecast that the cost model predicts for a request stream
+    under the server's policy (admission in arrival order while the head's
+    footprint fits, chunks that stop at the first member's end), with each
+    step costing a * computed_fraction * (cells of the members) + b.
+    Returns {rid: predicted seconds from arrival to forecast}."""
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    active = {}
+    now, used, out = 0.0, 0, {}
+    while pending or active:
+        while pending and (pending[0].arrival <= now or not active):
+            r = pending[0]
+            need = footprint(r.site, precision, flags)
+            if used + need > hbm_budget:
+                break
+            pending.popleft()
+            now = max(now, r.arrival)
+            active[r.rid] = [r, r.steps, need]
+            used += need
+        if not active:
+            now = pending[0].arrival
+            continue
+        n = min(chunk_steps, min(v[1] for v in active.values()))
+        cells = sum(v[0].site.cells for v in active.values())
+        now += n * (a * computed_fraction * cells + b)
+        for rid in list(active):
+            active[rid][1] -= n
+            if active[rid][1] == 0:
+                r, _, need = active.pop(rid)
+                used -= need
+                out[rid] = now - r.arrival
+    return out
 
 
 def percentiles(results, qs=(50, 99)):
