@@ -243,21 +243,25 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
 }
 
 
-// One tile g of domain d: read buffer b, write buffer b^1 (paper Eqs. 1-3
-// and the nest exchanges of Sec. IV-C for the tile's cells and faces).
+// Output rows [r0, r1) of tile g of domain d (0 <= r0 < r1 <= th, and the
+// first of them at most ny): read buffer b, write buffer b^1 (paper Eqs. 1-3
+// and the nest exchanges of Sec. IV-C for those rows' cells and faces).
+// Returns whether every value written was left bitwise unchanged (the
+// wavefront's part of the tile's stationarity); the caller records the flag.
 template <typename F>
-__device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int l)
+__device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int l, int r0, int r1)
 {
     const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
     const int x0 = tile_x(tl, L.tiles_x, L.tiles_y) * RTI_TW;
-    const int y0 = tile_y(tl, L.tiles_x, L.tiles_y) * d.th;
+    const int y0 = tile_y(tl, L.tiles_x, L.tiles_y) * d.th + r0;     // first output row
+    const int yend = y0 + (r1 - r0);                                 // one past the last
     const uint8_t info = d.tinfo[g];
     const bool has_child = (info & TI_CHILD) != 0;
     const bool root = (l == 0);
     const unsigned cmask = has_child ? d.tcmask[g] : 0u;   // children whose edges the tile injects
 
-    const int lane = (int)threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
     const int c = x0 - 2 + lane;
     const int nx = L.nx, ny = L.ny, P = L.pitch;
     const double r = L.r, eps = d.eps;
@@ -304,7 +308,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
     };
 
     const int t0 = y0 - 2;
-    const int t1 = min(y0 + d.th, ny + 1);     // last iteration; it writes row t1 - 1
+    const int t1 = min(yend, ny + 1);          // last iteration; it writes row t1 - 1
 
     // Output arrays through the same padded offsets.
     char *Eo_a = reinterpret_cast<char *>(Eo - pad);
@@ -361,7 +365,7 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
         e1 = (has_child && col_cell && row_cell && cur.R == cur.R) ? cur.R : e1;
         cur.e1 = e1;
         // a water level this tile writes (row t is written in the next iteration) left unchanged?
-        if (out_lane && col_cell && t >= y0 && t < y0 + d.th && t < ny) quiet = quiet && same_bits(e1, cur.E);
+        if (out_lane && col_cell && t >= y0 && t < yend && t < ny) quiet = quiet && same_bits(e1, cur.E);
 
         // Face quantities: x-face c of row t, y-face c at j = t.
         cur.e1L = from_left(e1);
@@ -449,15 +453,25 @@ __device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int
 #undef RTI_ROW
     }
 
-    // Stationarity history of the tile: bit1 <- bit0, bit0 <- this step left
-    // every value the tile writes (water levels, fluxes) bitwise unchanged.
-    const bool all_quiet = __all(quiet ? 1 : 0);
     if (__any(bad ? 1 : 0) && lane == 0) atomicOr(&d.status[0], 1);   // sticky: RTI_EDIVERGED on the host
-    if (lane == 0) {
-        const uint8_t old = d.tflag[g];
-        const uint8_t nw = (info & TI_PINNED) ? 0 : (uint8_t)(((old & 1u) << 1) | (all_quiet ? 1u : 0u));
-        d.tflag[g] = nw;
-    }
+    return __all(quiet ? 1 : 0);
+}
+
+// Stationarity history of tile g: bit1 <- bit0, bit0 <- this step left every
+// value the tile writes (water levels, fluxes) bitwise unchanged.
+__device__ __forceinline__ void record_quiet(const DomainDev &d, int g, bool all_quiet)
+{
+    const uint8_t old = d.tflag[g];
+    const uint8_t nw = (d.tinfo[g] & TI_PINNED) ? 0 : (uint8_t)(((old & 1u) << 1) | (all_quiet ? 1u : 0u));
+    d.tflag[g] = nw;
+}
+
+// A whole tile on one wavefront.
+template <typename F>
+__device__ __forceinline__ void fused_tile(const DomainDev &d, int b, int g, int l)
+{
+    const bool q = fused_rows<F>(d, b, g, l, 0, d.th);
+    if ((threadIdx.x & 63) == 0) record_quiet(d, g, q);
 }
 
 // Position in the active list of workgroup w's i-th tile.  Workgroups go to
@@ -474,12 +488,48 @@ __device__ __forceinline__ int slice_pos(int n_active, int slot)
     return pos < n_active ? pos : -1;
 }
 
-// One workgroup per active tile.
+// One workgroup per active tile.  Steps with at most split_max active tiles
+// are left to k_fused_split.
 template <typename F>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused(DomainDev d, int b)
 {
-    const int pos = slice_pos(min(d.count[b], d.ntiles), (int)(blockIdx.x >> 3));
+    const int n = min(d.count[b], d.ntiles);
+    if (n <= d.split_max) return;
+    const int pos = slice_pos(n, (int)(blockIdx.x >> 3));
     if (pos >= 0) fused_tile<F>(d, b, d.list[pos], d.lmeta[pos]);
+}
+
+// Steps with few active tiles (at most split_max): the machine is mostly
+// idle, and a tile's serial chain of th + 3 row iterations is the step's
+// floor.  Each active tile gets a workgroup of RTI_SPLIT wavefronts, each
+// computing a band of ceil(th / RTI_SPLIT) output rows with its own three
+// warm-up rows (recomputed from buffer b exactly as the whole tile would), so
+// the chain is that band plus three rows.  The bands' stationarity is AND-ed
+// in LDS into the tile's flag.  Steps with more active tiles are k_fused's.
+template <typename F>
+__global__ __launch_bounds__(64 * RTI_SPLIT) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_split(DomainDev d,
+                                                                                                       int b)
+{
+    const int n = min(d.count[b], d.ntiles);
+    if (n > d.split_max) return;
+    const int pos = slice_pos(n, (int)(blockIdx.x >> 3));
+    if (pos < 0) return;                                    // uniform over the workgroup
+    const int g = d.list[pos], l = d.lmeta[pos];
+    const LevelDev &L = level_of(d, l);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // the wavefront's band (uniform)
+    const int band = (d.th + RTI_SPLIT - 1) / RTI_SPLIT;
+    const int r0 = w * band, r1 = min(d.th, r0 + band);
+    const int y0 = tile_y(g - L.tile_base, L.tiles_x, L.tiles_y) * d.th;
+    bool q = true;
+    if (r0 < r1 && y0 + r0 <= L.ny) q = fused_rows<F>(d, b, g, l, r0, r1);
+    __shared__ int band_quiet[RTI_SPLIT];
+    if ((threadIdx.x & 63) == 0) band_quiet[w] = q ? 1 : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int all = 1;
+        for (int k = 0; k < RTI_SPLIT; ++k) all &= band_quiet[k];
+        record_quiet(d, g, all != 0);
+    }
 }
 
 // A persistent grid: every workgroup loops over tiles.  (The loop costs the
@@ -488,6 +538,7 @@ template <typename F>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_loop(DomainDev d, int b)
 {
     const int n_active = min(d.count[b], d.ntiles);
+    if (n_active <= d.split_max) return;
     for (int slot = (int)(blockIdx.x >> 3);; slot += (int)(gridDim.x >> 3)) {
         const int pos = slice_pos(n_active, slot);
         if (pos < 0) break;
@@ -704,7 +755,7 @@ hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int
 
 // grid: workgroups (a multiple of 8), at most one per tile; fewer make a
 // persistent grid.
-hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s)
+hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s, bool every_tile)
 {
     const bool loop = grid < (d.ntiles + 7) / 8 * 8;
     if (d.bulk32) {
@@ -714,6 +765,15 @@ hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s)
         if (loop) hipLaunchKernelGGL(k_fused_loop<double>, dim3(grid), dim3(64), 0, s, d, b);
         else hipLaunchKernelGGL(k_fused<double>, dim3(grid), dim3(64), 0, s, d, b);
     }
+    hipError_t e = hipGetLastError();
+    // with every tile listed the split kernel has nothing to do unless the domain is that small
+    if (e != hipSuccess || d.split_max <= 0 || (every_tile && d.ntiles > d.split_max)) return e;
+    // the split kernel: one workgroup per list position up to split_max, 8 XCD slices
+    const int sgrid = (d.split_max + 7) / 8 * 8;
+    if (d.bulk32)
+        hipLaunchKernelGGL(k_fused_split<float>, dim3(sgrid), dim3(64 * RTI_SPLIT), 0, s, d, b);
+    else
+        hipLaunchKernelGGL(k_fused_split<double>, dim3(sgrid), dim3(64 * RTI_SPLIT), 0, s, d, b);
     return hipGetLastError();
 }
 

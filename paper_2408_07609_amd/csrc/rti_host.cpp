@@ -540,8 +540,10 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
         HIP_TRY(launch_momentum(D->dev, b, s));
         HIP_TRY(launch_jnq(D->dev, b, s));
     } else {
-        HIP_TRY(launch_active(D->dev, b, (every_tile || (D->flags & RTI_FLAG_NO_ACTIVE)) ? 1 : 0, s));
-        HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s));
+        const bool all = every_tile || (D->flags & RTI_FLAG_NO_ACTIVE);
+        HIP_TRY(launch_active(D->dev, b, all ? 1 : 0, s));
+        HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s,
+                             all));
     }
     return RTI_OK;
 }
@@ -791,6 +793,9 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         for (int s = 0; s < 4; ++s) dv.bc[s] = desc->bc[s];
         dv.eps = desc->dry_eps;
         dv.bulk32 = (desc->precision == RTI_FP32_BULK) ? 1 : 0;
+        // sparse steps (active tiles that fill at most 3 wavefronts per SIMD once split)
+        // run the split kernel; the persistent-grid option keeps the one-wavefront tiles
+        dv.split_max = (desc->flags & RTI_FLAG_PERSISTENT) ? 0 : 3 * D->cu_count;
         dv.g = desc->g;
         dv.fc = 0.5 * desc->dt * desc->g * desc->manning_n * desc->manning_n;
         D->lvh.assign(dv.nlev, LevelDev{});
@@ -1109,7 +1114,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
             if (e == hipSuccess) e = hipEventRecord(ev[1], D->stream);
             if (e == hipSuccess)
                 e = launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count),
-                                 D->stream);
+                                 D->stream, (D->flags & RTI_FLAG_NO_ACTIVE) != 0);
             if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
             kinds[0] = K_ACTIVE; kinds[1] = K_FUSED;
             nk = 2;

@@ -30,6 +30,8 @@
 #define RTI_PD 2
 #endif
 #define RTI_NS (RTI_PD + 3)
+// Wavefronts per tile in the split kernel of sparse steps (each a band of rows).
+#define RTI_SPLIT 4
 // Zero rows above the last row of every array (the prefetch reads up to row
 // ny + RTI_PD + 2) and below row 0 (the warm-up reads down to row -3).
 #define RTI_PAD_TOP (RTI_PD + 3)
@@ -96,6 +98,7 @@ struct DomainDev {
     int32_t bc[4];
     int32_t bulk32;                        // 1: h, maxima, M, N stored and the momentum computed in FP32
     int32_t max_ring, max_edge;            // longest child ring (parent cells) and child edge (faces)
+    int32_t split_max;                     // steps with at most this many active tiles run k_fused_split (0: never)
     double eps, fc, g;                     // dry threshold, dt/2 g n^2, gravity
     const uint8_t *tinfo;                  // ntiles static bits (TI_*)
     uint8_t *tflag;                        // ntiles: bit0 stationary in the last step (nothing it writes changed), bit1 in the one before
@@ -174,7 +177,8 @@ hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_init_level(const LevelDev &L, int bulk32, const InitSource &sp, hipStream_t s);
 // Also computes the ring means of the step (LevelDev::ring).
 hipError_t launch_active(const DomainDev &d, int b, int all_active, hipStream_t s);
-hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s);
+// every_tile: the step's list holds every tile (RTI_FLAG_NO_ACTIVE, the autotuner's trials).
+hipError_t launch_fused(const DomainDev &d, int b, int grid, hipStream_t s, bool every_tile);
 hipError_t launch_active_batch(const BatchDev &bd, int flip, int all_active, int bulk32, hipStream_t s);
 hipError_t launch_fused_batch(const BatchDev &bd, int flip, int bulk32, int grid, hipStream_t s);
 hipError_t launch_probe_math(int op, const double *x, double *y, int64_t n, hipStream_t s);

@@ -184,7 +184,13 @@ def fit_cost_model(chunks):
     A = np.array([[c[3] / c[0], 1.0] for c in chunks if c[0] > 0])
     y = np.array([c[1] / c[0] for c in chunks if c[0] > 0])
     w = np.sqrt(np.array([c[0] for c in chunks if c[0] > 0], dtype=np.float64))   # long chunks count more
-    (a, b), *_ = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)
+    Aw, yw = A * w[:, None], y * w
+    (a, b), *_ = np.linalg.lstsq(Aw, yw, rcond=None)
+    # both costs are non-negative: on the boundary, fit the other one alone
+    if a < 0:
+        a, b = 0.0, float(np.dot(Aw[:, 1], yw) / np.dot(Aw[:, 1], Aw[:, 1]))
+    elif b < 0:
+        a, b = float(np.dot(Aw[:, 0], yw) / np.dot(Aw[:, 0], Aw[:, 0])), 0.0
     return float(a), float(b)
 
 
