@@ -195,7 +195,7 @@ def bench_batch(args):
 
     import scenarios
     from paper_2408_07609_amd import (RTI_FLAG_NO_ACTIVE, RTI_FLAG_NO_GRAPH, RTI_FLAG_PERSISTENT, RTI_FP32_BULK, RTI_FP64,
-                                      Batch)
+                                      Batch, autotune_batch_rows)
 
     prec = RTI_FP32_BULK if args.precision == "fp32-bulk" else RTI_FP64
     scs = scenarios.c4()
@@ -209,13 +209,25 @@ def bench_batch(args):
     def build(precision, tune):
         ds = [make_domain(sc, precision, member_flags) for sc in scs]
         rows = []
-        if tune:
+        if tune and args.tile_rows:
             for d in ds:
-                rows.append(d.autotune(8)[0])
+                d.set_tile_rows(args.tile_rows)
+                rows.append(args.tile_rows)
+        elif tune:
+            # one height for the whole batch, tuned on throwaway copies of the members
+            copies = [make_domain(sc, precision, member_flags) for sc in scs]
+            best, ms = autotune_batch_rows(copies, 8)
+            for c in copies:
+                c.close()
+            del copies
+            log(f"batch autotuner: {best} rows ({ms:.3f} ms per step, every tile computed)")
+            for d in ds:
+                d.set_tile_rows(best)
+                rows.append(best)
         return ds, rows
 
     ds, rows = build(prec, True)
-    log(f"autotuned tile rows: {dict(collections.Counter(rows))}")
+    log(f"tile rows: {dict(collections.Counter(rows))}")
     batch = Batch(ds, flags=(RTI_FLAG_PERSISTENT if args.persistent else 0)
                   | (args.flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_NO_GRAPH)))
     batch.step(args.warmup)

@@ -532,3 +532,24 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def autotune_batch_rows(domains, nsteps=8, candidates=(6, 8, 10, 12, 16, 24)):
+    """One tile height for every member of a batch: for each candidate, set
+    it on every member, step the batch twice untimed and time nsteps batch
+    steps with every tile computed (rti_batch_profile), and keep the fastest.
+    A member's own autotuner picks short tiles for a small domain alone (more
+    wavefronts for it), but in a batch the members' tiles already fill the
+    GPU, and short tiles only add recomputed warm-up rows.  The trials step
+    the domains: pass copies made for tuning (same shapes), not the domains
+    to be run.  Returns (rows, fused-kernel ms per step at that height)."""
+    best = None
+    for rows in candidates:
+        for d in domains:
+            d.set_tile_rows(rows)
+        with Batch(domains, flags=RTI_FLAG_NO_ACTIVE) as b:
+            b.step(2)
+            fused_ms, _, _ = b.profile(nsteps)
+        if best is None or fused_ms < best[1]:
+            best = (rows, fused_ms)
+    return best

@@ -243,3 +243,24 @@ def test_member_from_another_stream_is_adopted():
     d.sync()
     assert d.steps == 90
     assert_same(snapshot(d), snapshot(ref), "adopted member")
+
+
+def test_batch_autotuner_picks_one_height():
+    """The batch-wide autotuner sets one candidate height on every member and
+    reports a positive time; running the members at that height gives
+    bitwise the results of the default height (the height changes only the
+    decomposition)."""
+    from paper_2408_07609_amd import Batch, autotune_batch_rows
+    scs = members()[:3]
+    copies = [make(sc) for sc in scs]
+    rows, ms = autotune_batch_rows(copies, 3, candidates=(6, 12))
+    assert rows in (6, 12) and ms > 0
+    assert all(c.tile_rows == 12 for c in copies)          # the last candidate stays set
+    a = [make(sc, rows=rows) for sc in scs]
+    b = [make(sc) for sc in scs]
+    with Batch(a) as ba:
+        ba.step(60)
+    with Batch(b) as bb:
+        bb.step(60)
+    for x, y in zip(a, b):
+        assert_same(snapshot(x), snapshot(y), f"batch at {rows} rows vs the default")

@@ -4,8 +4,9 @@ written by tests/golden/make_golden.py (which calls only the oracle):
 
 - configuration 2 (4 levels, 10.02 M cells, 3 m uplift), all 18,000 steps of
   0.2 s = 3600 s;
-- configuration 3's grid (5 levels, 47.2 M cells; the 10 m level floods
-  within the window) with the uplift 30 km offshore, 3000 steps.
+- configuration 3's grid (5 levels, 47.2 M cells) with the uplift 10 km
+  offshore, so that the 30 m and 10 m levels flood within the window, 3000
+  steps.
 
 Both sides start from the oracle's initial level (the source's exp, sin and
 cos are not correctly rounded on either side, so rti_set_source matches the
