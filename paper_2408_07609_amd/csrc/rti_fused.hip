@@ -88,7 +88,7 @@ struct FaceQ {
 };
 
 // The wet/dry rule and the depth are evaluated in FP64 on the FP64 levels.
-template <typename F>
+template <typename F, bool Friction = true>
 __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, double hb, double eb, double eps,
                                           F f, F cr, F fc)
 {
@@ -106,7 +106,7 @@ __device__ __forceinline__ FaceQ<F> face_q(bool interior, double ha, double ea, 
     o.cr = cr;
     o.q = over_depth(f, f, iD);
     o.p = over_depth(f, cr, iD);
-    o.fr = friction(fc, f, cr, Df, iD);
+    o.fr = Friction ? friction(fc, f, cr, Df, iD) : F(0);   // only the faces the tile writes need it
     return o;
 }
 
@@ -338,8 +338,13 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
     bool quiet = true;
     bool bad = false;            // a non-finite value written (the divergence watchdog)
 
-    auto do_row = [&](auto kc, int t) {
+    // Phase of a row (compile time): 0 the first warm-up row (y0 - 2: only its
+    // new water level is read, by the y-faces of row y0 - 1), 1 the second
+    // (y0 - 1: its faces are read as neighbours, never updated, so their
+    // friction is not needed), 2 the rows from y0 on.
+    auto do_row = [&](auto kc, auto phc, int t) {
         constexpr int K = decltype(kc)::value;
+        constexpr int PH = decltype(phc)::value;
         RowW<F> &cur = w[K];
         const RowW<F> &p = w[(K + NS - 1) % NS];
         const RowW<F> &pp = w[(K + NS - 2) % NS];
@@ -372,16 +377,18 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
         cur.HL = from_left(H_t);
         cur.NyL = from_left(cur.Ny);
         const F nb = F(0.25) * ((p.NyL + cur.NyL) + (p.Ny + cur.Ny));
-        cur.x = face_q<F>(col_xint && row_cell, cur.HL, cur.e1L, H_t, e1, eps, cur.Mx, nb, fcf);
+        if constexpr (PH > 0)
+            cur.x = face_q<F, (PH == 2)>(col_xint && row_cell, cur.HL, cur.e1L, H_t, e1, eps, cur.Mx, nb, fcf);
         const F mb = F(0.25) * ((p.Mx + p.MxR) + (cur.Mx + cur.MxR));
-        cur.y = face_q<F>(col_cell && t >= 1 && t <= ny - 1, p.H, p.e1, H_t, e1, eps, p.Ny, mb, fcf);
+        if constexpr (PH > 0)
+            cur.y = face_q<F, (PH == 2)>(col_cell && t >= 1 && t <= ny - 1, p.H, p.e1, H_t, e1, eps, p.Ny, mb, fcf);
 
         // Momentum and outputs of row (x-faces, cells) / face (y-faces) rr = t-1.
         // The momentum of both faces is evaluated on every lane (inactive
         // faces carry safe values) and the rule selects the result; only the
         // stores depend on the lane.
         const int rr = t - 1;
-        if (rr >= y0 && rr <= ny) {
+        if (PH == 2 && rr >= y0 && rr <= ny) {
             const FaceQ<F> &xp = p.x, &yp = p.y;
             const int xl_act = dpp_left_i(xp.act), xr_act = dpp_right_i(xp.act);
             const F xl_f = from_left(xp.f), xr_f = from_right(xp.f);
@@ -424,10 +431,14 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
         }
     };
 
-    for (int t = t0;; t += NS) {
-#define RTI_ROW(K)                                              \
-        do_row(std::integral_constant<int, (K)>{}, t + (K));    \
-        if (t + (K) + 1 > t1) break;
+    // The two warm-up rows, then rows y0 .. t1 - 1 in slots 2, 3, ..., 1 (the
+    // loop runs at least to t0 + 3: t1 >= y0 + 1 since y0 <= ny).
+    do_row(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, t0);
+    do_row(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}, t0 + 1);
+    for (int t = t0 + 2;; t += NS) {
+#define RTI_ROW(J)                                                                                     \
+        do_row(std::integral_constant<int, ((J) + 2) % NS>{}, std::integral_constant<int, 2>{}, t + (J)); \
+        if (t + (J) + 1 > t1) break;
         RTI_ROW(0)
         RTI_ROW(1)
         RTI_ROW(2)
