@@ -46,7 +46,7 @@ class _Level(ctypes.Structure):
                 ("dx", ctypes.c_double), ("ox", ctypes.c_double), ("oy", ctypes.c_double),
                 ("h", ctypes.c_void_p), ("eta", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("N", ctypes.c_void_p), ("zmax", ctypes.c_void_p), ("M2", ctypes.c_void_p),
-                ("N2", ctypes.c_void_p), ("clip", ctypes.c_void_p)]
+                ("N2", ctypes.c_void_p), ("clip", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
 
 
 class _Domain(ctypes.Structure):
@@ -112,18 +112,62 @@ def threads() -> int:
 OK, EINVAL, ECFL, ENEST = 0, -1, -4, -5
 
 
+def level_mask(lv):
+    """Cells inside level lv (ny x nx bool): its mask, or every cell."""
+    m = lv.get("mask")
+    if m is None:
+        return np.ones((lv["ny"], lv["nx"]), dtype=bool)
+    return np.asarray(m).reshape(lv["ny"], lv["nx"]) != 0
+
+
+def coverage(lv):
+    """Parent cells covered by child lv, over its footprint (ny/3 x nx/3 bool):
+    those whose 3x3 child cells are inside it."""
+    return level_mask(lv)[::3, ::3]
+
+
+def _dilate(a, r):
+    """Cells within Chebyshev distance r of a True cell of a."""
+    ny, nx = a.shape
+    p = np.pad(a, r)
+    out = np.zeros_like(a)
+    for dj in range(2 * r + 1):
+        for di in range(2 * r + 1):
+            out |= p[dj:dj + ny, di:di + nx]
+    return out
+
+
 def validate(levels, dx0, dt, g=9.81):
     """Check a nested layout against the paper's rules; returns an error code.
 
-    levels: list of dicts with nx, ny, parent, off_i, off_j, h (ny x nx array).
-    - Eq. (4): dx_l / dt >= sqrt(2 g h_max,l) on every level (h_max over sea cells).
+    levels: list of dicts with nx, ny, parent, off_i, off_j, h (ny x nx array)
+    and, on a child, an optional mask (ny x nx, 1 = cell inside the level).
+    - Eq. (4): dx_l / dt >= sqrt(2 g h_max,l) on every level (h_max over sea
+      cells inside the level).
     - 3:1 inclusive nesting (Sec. II-A): child nx, ny divisible by 3, the child
       footprint inside its parent; reading: at least 3 parent cells of margin on
       every side, a footprint of at least 3x3 parent cells, siblings apart by
       at least 3 parent cells, parents listed before children.
+    - A mask (the union of touching blocks of one resolution, Sec. II-A and
+      Table 1) is 0 or 1 and constant over every 3x3 child block, covers at
+      least one parent cell, and the root has none; every parent cell within 3
+      cells of a covered one lies inside the parent.
     """
     if not levels or dt <= 0 or dx0 <= 0:
         return EINVAL
+    for k, lv in enumerate(levels):
+        m = lv.get("mask")
+        if m is None:
+            continue
+        m = np.asarray(m)
+        if k == 0 or m.size != lv["nx"] * lv["ny"] or not np.isin(m, (0, 1)).all():
+            return ENEST
+        if lv["nx"] % 3 or lv["ny"] % 3:
+            return ENEST
+        m = m.reshape(lv["ny"], lv["nx"])
+        cov = m[::3, ::3]
+        if not cov.any() or not np.array_equal(np.repeat(np.repeat(cov, 3, axis=0), 3, axis=1), m):
+            return ENEST
     dxs = []
     for k, lv in enumerate(levels):
         nx, ny, p = lv["nx"], lv["ny"], lv["parent"]
@@ -144,6 +188,11 @@ def validate(levels, dx0, dt, g=9.81):
                 return ENEST
             if lv["off_i"] + fw > P["nx"] - 3 or lv["off_j"] + fh > P["ny"] - 3:
                 return ENEST
+            if P.get("mask") is not None:     # 3 cells of margin inside the parent's own cells
+                near = np.zeros((P["ny"], P["nx"]), dtype=bool)
+                near[lv["off_j"]:lv["off_j"] + fh, lv["off_i"]:lv["off_i"] + fw] = coverage(lv)
+                if (_dilate(near, 3) & ~level_mask(P)).any():
+                    return ENEST
             dxs.append(dxs[p] / 3.0)
     for k, lv in enumerate(levels):
         for q in range(k + 1, len(levels)):
@@ -157,7 +206,7 @@ def validate(levels, dx0, dt, g=9.81):
             if ax0 < bx1 and bx0 < ax1 and ay0 < by1 and by0 < ay1:
                 return ENEST
     for k, lv in enumerate(levels):
-        hmax = float(np.max(lv["h"]))
+        hmax = float(np.max(np.asarray(lv["h"]).reshape(lv["ny"], lv["nx"])[level_mask(lv)]))
         if hmax > 0 and dxs[k] / dt < np.sqrt(2.0 * g * hmax):
             return ECFL
     return OK
@@ -167,7 +216,9 @@ class OracleDomain:
     """A nested domain held in numpy arrays and stepped by the C oracle.
 
     Arrays per level (row-major, j slowest): h, eta, zmax (ny, nx);
-    M (ny, nx+1) on x-faces; N (ny+1, nx) on y-faces.
+    M (ny, nx+1) on x-faces; N (ny+1, nx) on y-faces.  Cells outside a
+    masked level hold eta = 0 and zmax = 0 whatever is set there (the step
+    never changes them).
     """
 
     def __init__(self, levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 0, 0),
@@ -197,13 +248,15 @@ class OracleDomain:
                 "M": np.zeros((ny, nx + 1)), "N": np.zeros((ny + 1, nx)),
                 "M2": np.zeros((ny, nx + 1)), "N2": np.zeros((ny + 1, nx)),
                 "clip": np.zeros((ny, nx)) if track_clip else None,
+                "mask": (np.ascontiguousarray(level_mask(lv), dtype=np.uint8) if lv.get("mask") is not None
+                         else None),
             }
             self.arrays.append(a)
             s = self._lv[k]
             s.nx, s.ny, s.parent = nx, ny, p
             s.off_i, s.off_j = int(lv.get("off_i", 0)), int(lv.get("off_j", 0))
             s.dx, s.ox, s.oy = dx, ox, oy
-            for f in ("h", "eta", "M", "N", "zmax", "M2", "N2", "clip"):
+            for f in ("h", "eta", "M", "N", "zmax", "M2", "N2", "clip", "mask"):
                 setattr(s, f, a[f].ctypes.data if a[f] is not None else None)
         self.dx = dxs
         self.origin = list(zip(oxs, oys))
@@ -232,10 +285,21 @@ class OracleDomain:
             a["M"][...] = 0.0
             a["N"][...] = 0.0
             a["zmax"][...] = np.where(h > 0, a["eta"], h + a["eta"])
+        for k in range(self.nlev):
+            self._outside_zero(k)
         self._d.steps = 0
+
+    def _outside_zero(self, k):
+        a = self.arrays[k]
+        if a["mask"] is not None:
+            out = a["mask"] == 0
+            a["eta"][out] = 0.0
+            a["zmax"][out] = 0.0
 
     def set_source(self, xc, yc, a, b, theta, amp, shape):
         self._lib.ora_set_source(ctypes.byref(self._d), xc, yc, a, b, theta, amp, int(shape))
+        for k in range(self.nlev):
+            self._outside_zero(k)
 
     def set_eta(self, k, eta0):
         """Raw initial level on level k (clipped to the ground); zero fluxes; maxima reset."""
@@ -247,6 +311,7 @@ class OracleDomain:
         a["M"][...] = 0.0
         a["N"][...] = 0.0
         a["zmax"][...] = np.where(h > 0, e, h + e)
+        self._outside_zero(k)
         self._d.steps = 0
 
     def set_state(self, k, eta=None, M=None, N=None, zmax=None):
@@ -254,6 +319,7 @@ class OracleDomain:
         for name, v in (("eta", eta), ("M", M), ("N", N), ("zmax", zmax)):
             if v is not None:
                 a[name][...] = np.asarray(v, dtype=np.float64).reshape(a[name].shape)
+        self._outside_zero(k)
 
     def get_state(self, k):
         a = self.arrays[k]

@@ -30,6 +30,15 @@
  *   N            : nx*(ny+1) y-faces,     face (i,j)   between cells (i,j-1),(i,j)
  * h > 0 is still-water depth, h <= 0 is land with elevation -h.
  *
+ * A child level may leave cells of its rectangle out (mask): the union of
+ * touching blocks of one resolution (Sec. II-A, Table 1: a resolution is
+ * covered by several rectangular blocks) held in one array, so that blocks
+ * that share an edge exchange exactly, as one grid.  The mask is constant
+ * over each child 3x3 block, so each parent cell is either covered by the
+ * child (its 9 child cells inside) or not.  A cell outside takes no part in
+ * the step: no face touching it carries a computed flux, and the
+ * exchanges follow the covered region's boundary instead of the rectangle's.
+ *
  * Arithmetic: IEEE binary64, round to nearest, built with -ffp-contract=off so
  * no multiply-add is fused.  Sums are grouped exactly as written.  Every
  * operation of the step is correctly rounded: +, -, *, / and sqrt by IEEE, and
@@ -41,7 +50,10 @@
  * Parity unpinned (no pin beyond the lake-at-rest, symmetry and the oracle
  * itself fixes them, because the paper is silent): the one-wet-side face depth
  * of the wet/dry rule, the neighbour-skip rule of the advection term, the
- * wet-only average of the child->parent exchange.
+ * wet-only average of the child->parent exchange, and on a masked level the
+ * ring cell at an inner corner of the covered region (a covered parent cell
+ * whose only uncovered neighbour is diagonal takes the child mean, as a
+ * rectangle's corner cells do).
  */
 #include <math.h>
 #include <stddef.h>
@@ -61,6 +73,7 @@ typedef struct {
     double *h, *eta, *M, *N, *zmax;
     double *M2, *N2;        /* scratch for the new fluxes, same shapes as M, N */
     double *clip;           /* optional (may be NULL): accumulated clipped depth per cell */
+    const uint8_t *mask;    /* optional (NULL: every cell): 1 = cell inside the level, nx*ny */
 } ora_level;
 
 typedef struct {
@@ -74,6 +87,20 @@ typedef struct {
 #define CELL(L, i, j)  ((size_t)(j) * (size_t)(L)->nx + (size_t)(i))
 #define XF(L, i, j)    ((size_t)(j) * (size_t)((L)->nx + 1) + (size_t)(i))
 #define YF(L, i, j)    ((size_t)(j) * (size_t)(L)->nx + (size_t)(i))
+
+/* Is cell (i, j) of level L inside it (not left out by its mask)? */
+static int inside(const ora_level *L, int i, int j)
+{
+    return !L->mask || L->mask[CELL(L, i, j)];
+}
+
+/* Is parent cell (I, J), counted from child C's origin, covered by C (the
+ * 3x3 child cells below it inside C)? */
+static int covered(const ora_level *C, int I, int J)
+{
+    if (I < 0 || J < 0 || I >= C->nx / 3 || J >= C->ny / 3) return 0;
+    return inside(C, 3 * I, 3 * J);
+}
 
 int ora_threads(void)
 {
@@ -176,6 +203,7 @@ void ora_mass(ora_domain *d, int l)
     #pragma omp parallel for schedule(static)
     for (int j = 0; j < L->ny; j++) {
         for (int i = 0; i < L->nx; i++) {
+            if (!inside(L, i, j)) continue;
             double e = L->eta[CELL(L, i, j)]
                      - r * ((L->M[XF(L, i + 1, j)] - L->M[XF(L, i, j)])
                           + (L->N[YF(L, i, j + 1)] - L->N[YF(L, i, j)]));
@@ -191,7 +219,9 @@ void ora_mass(ora_domain *d, int l)
 
 /* ------------------------------------------------------------------------ */
 /* Child -> parent water level (Sec. IV-C, the JNZSND exchange): every parent
- * cell in the outermost ring of the child's footprint takes the mean of the
+ * cell on the ring of the child's footprint (a covered parent cell with a
+ * parent cell among its 8 neighbours that the child does not cover; for a
+ * rectangular child the outermost ring, corners once) takes the mean of the
  * 3x3 child cells it covers, summed j outer, i inner.
  * Reading: only wet child cells (h + eta > eps) enter the mean (a dry child
  * cell holds its ground level, which is not a water level); with no wet child
@@ -204,7 +234,12 @@ void ora_jnz(ora_domain *d, int c)
     const int fw = C->nx / 3, fh = C->ny / 3;
     for (int J = 0; J < fh; J++) {
         for (int I = 0; I < fw; I++) {
-            if (!(I == 0 || I == fw - 1 || J == 0 || J == fh - 1)) continue;
+            if (!covered(C, I, J)) continue;
+            int ring = 0;
+            for (int dj = -1; dj <= 1; dj++)
+                for (int di = -1; di <= 1; di++)
+                    if (!covered(C, I + di, J + dj)) ring = 1;
+            if (!ring) continue;
             double s = 0.0;
             int k = 0;
             for (int jj = 3 * J; jj < 3 * J + 3; jj++) {
@@ -251,14 +286,18 @@ static int face_depth(double ha, double ea, double hb, double eb, double eps, do
     return 1;
 }
 
+/* A face touching a cell outside the level is, like the level's own edge
+ * faces, never active: its flux comes from the parent (ora_jnq) or is 0. */
 static int xface_depth(const ora_level *L, double eps, int i, int j, double *D)
 {
+    if (!inside(L, i - 1, j) || !inside(L, i, j)) return 0;
     return face_depth(L->h[CELL(L, i - 1, j)], L->eta[CELL(L, i - 1, j)],
                       L->h[CELL(L, i, j)], L->eta[CELL(L, i, j)], eps, D);
 }
 
 static int yface_depth(const ora_level *L, double eps, int i, int j, double *D)
 {
+    if (!inside(L, i, j - 1) || !inside(L, i, j)) return 0;
     return face_depth(L->h[CELL(L, i, j - 1)], L->eta[CELL(L, i, j - 1)],
                       L->h[CELL(L, i, j)], L->eta[CELL(L, i, j)], eps, D);
 }
@@ -461,22 +500,26 @@ void ora_bc_root(ora_domain *d)
 
 /* ------------------------------------------------------------------------ */
 /* Parent -> child fluxes (Sec. IV-A, the JNQ exchange; the interpolation is a
- * reading): each child boundary face takes the flux per unit width of the
- * parent face it lies on.  Three child faces of width dx/3 then carry exactly
- * the parent face's discharge. */
+ * reading): each child face on the boundary of the child's footprint (a
+ * parent face between a covered and an uncovered parent cell; for a
+ * rectangular child the four edges) takes the flux per unit width of the
+ * parent face it lies on, on all 3 child faces of that parent face.  Three
+ * child faces of width dx/3 then carry exactly the parent face's discharge. */
 void ora_jnq(ora_domain *d, int c)
 {
     ora_level *C = &d->lv[c];
     ora_level *P = &d->lv[C->parent];
     const int I0 = C->off_i, J0 = C->off_j, fw = C->nx / 3, fh = C->ny / 3;
-    for (int jf = 0; jf < C->ny; jf++) {
-        C->M[XF(C, 0, jf)] = P->M[XF(P, I0, J0 + jf / 3)];
-        C->M[XF(C, C->nx, jf)] = P->M[XF(P, I0 + fw, J0 + jf / 3)];
-    }
-    for (int i = 0; i < C->nx; i++) {
-        C->N[YF(C, i, 0)] = P->N[YF(P, I0 + i / 3, J0)];
-        C->N[YF(C, i, C->ny)] = P->N[YF(P, I0 + i / 3, J0 + fh)];
-    }
+    for (int J = 0; J < fh; J++)                 /* x-faces: between parent cells (I-1, J) and (I, J) */
+        for (int I = 0; I <= fw; I++)
+            if (covered(C, I - 1, J) != covered(C, I, J))
+                for (int k = 0; k < 3; k++)
+                    C->M[XF(C, 3 * I, 3 * J + k)] = P->M[XF(P, I0 + I, J0 + J)];
+    for (int J = 0; J <= fh; J++)                /* y-faces: between parent cells (I, J-1) and (I, J) */
+        for (int I = 0; I < fw; I++)
+            if (covered(C, I, J - 1) != covered(C, I, J))
+                for (int k = 0; k < 3; k++)
+                    C->N[YF(C, 3 * I + k, 3 * J)] = P->N[YF(P, I0 + I, J0 + J)];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -488,6 +531,7 @@ void ora_max(ora_domain *d, int l)
     const size_t n = (size_t)L->nx * (size_t)L->ny;
     #pragma omp parallel for schedule(static)
     for (size_t c = 0; c < n; c++) {
+        if (L->mask && !L->mask[c]) continue;
         double h = L->h[c], e = L->eta[c];
         double v = (h > 0.0) ? e : h + e;
         if (v > L->zmax[c]) L->zmax[c] = v;

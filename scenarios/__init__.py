@@ -65,7 +65,9 @@ class Scenario:
 
     @property
     def cells(self) -> int:
-        return int(sum(lv["nx"] * lv["ny"] for lv in self.levels))
+        """Cells of all levels (inside cells only, on a masked level)."""
+        return int(sum(lv["nx"] * lv["ny"] if lv.get("mask") is None else int(np.count_nonzero(lv["mask"]))
+                       for lv in self.levels))
 
     def level_dx(self, k: int) -> float:
         dx = self.dx0
@@ -108,7 +110,8 @@ class Scenario:
     def check_cfl(self):
         """Eq. (4) of the paper per level: dx/dt >= sqrt(2 g h_max)."""
         for k, lv in enumerate(self.levels):
-            hmax = float(np.max(lv["h"]))
+            h = lv["h"] if lv.get("mask") is None else lv["h"][np.asarray(lv["mask"]) != 0]
+            hmax = float(np.max(h))
             lim = (self.level_dx(k) / self.dt) ** 2 / (2.0 * self.g)
             assert hmax <= lim, f"{self.name}: level {k} depth {hmax:.1f} m exceeds CFL limit {lim:.1f} m"
 
@@ -263,6 +266,46 @@ def c3_nearshore(seed: int = 3) -> Scenario:
     src = sc.source
     sc.name = "c3-nested5-nearshore"
     sc.source = Source(src.xc + 140e3, src.yc, src.a, src.b, src.theta, src.amp, src.shape)
+    return sc
+
+
+def union_level(parent, rects):
+    """A level made of touching blocks of one resolution (Sec. II-A, Table 1),
+    held as one array over their bounding box with an inside mask.  rects:
+    (i0, j0, w, h) per block, in cells of the parent level."""
+    i0 = min(r[0] for r in rects)
+    j0 = min(r[1] for r in rects)
+    i1 = max(r[0] + r[2] for r in rects)
+    j1 = max(r[1] + r[3] for r in rects)
+    mask = np.zeros((3 * (j1 - j0), 3 * (i1 - i0)), dtype=np.uint8)
+    for (a, b, w, h) in rects:
+        mask[3 * (b - j0):3 * (b - j0 + h), 3 * (a - i0):3 * (a - i0 + w)] = 1
+    lv = _level(3 * (i1 - i0), 3 * (j1 - j0), parent, i0, j0)
+    lv["mask"] = mask
+    return lv
+
+
+def small_union(seed: int = 23, grandchild: bool = True) -> Scenario:
+    """An L-shaped level of two touching blocks over the shoreline of a small
+    coast: a 54x48 root at 810 m; at 270 m an 18x9 block (parent cells) with a
+    9x9 block on top of its west half, as one masked level; at 90 m a 27x27
+    block that spans both 270 m blocks."""
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 54, 48
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.6 * Lx, Ly, wiggle=0.04 * Ly,
+                   knots=[(0.0, 0.0), (0.1 * Lx, 20.0), (0.4 * Lx, 200.0), (1e12, 200.0)],
+                   zmax=5.0, slope=5.0 / (0.05 * Lx), Lx=Lx, nbumps=0, scale=1)
+    sc = Scenario("small-union", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=0)
+    cx = int(round(float(coast.xc(np.array([Ly / 2]))[0]) / dx0))
+    cy = ny0 // 2
+    sc.levels.append(union_level(0, [(cx - 9, cy - 9, 18, 9), (cx - 9, cy, 9, 9)]))
+    if grandchild:
+        sc.levels.append(_level(27, 27, 1, 6, 22))     # child cells [6, 15) x [22, 31): across the junction
+    _fill_depths(sc, coast)
+    sc.source = Source((cx - 0.03 * nx0) * dx0, Ly / 2, 0.08 * Lx, 0.3 * Ly, 0.0, 1.5, COS2_ELLIPSE)
+    sc.check_cfl()
     return sc
 
 

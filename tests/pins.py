@@ -89,11 +89,13 @@ def pin_closed_mass(lib=None, quick=False):
 
 
 def footprint_masks(sc_levels):
-    """Cells counted once in a nested volume: every cell not covered by a child."""
-    masks = [np.ones((lv["ny"], lv["nx"]), dtype=bool) for lv in sc_levels]
+    """Cells counted once in a nested volume: every cell inside its level
+    and not covered by a child."""
+    masks = [oracle.level_mask(lv).copy() for lv in sc_levels]
     for lv in sc_levels[1:]:
         p = lv["parent"]
-        masks[p][lv["off_j"]:lv["off_j"] + lv["ny"] // 3, lv["off_i"]:lv["off_i"] + lv["nx"] // 3] = False
+        masks[p][lv["off_j"]:lv["off_j"] + lv["ny"] // 3, lv["off_i"]:lv["off_i"] + lv["nx"] // 3] &= \
+            ~oracle.coverage(lv)
     return masks
 
 
@@ -520,6 +522,279 @@ def pin_validation(lib=None, quick=False):
 
 
 # ---------------------------------------------------------------------------
+# Levels made of touching blocks (a masked level, Sec. II-A and Table 1).
+OUTSIDE_DEPTH = 5000.0      # the depth given to cells outside a level: deep enough to break Eq. (4) if counted
+
+
+def masked_twin(lv, pad):
+    """Level lv held as a masked level: its array grown by pad parent cells
+    on every side, its own cells inside, the new ones outside (with a depth
+    that would change every result if the step read it)."""
+    nx, ny = lv["nx"] + 6 * pad, lv["ny"] + 6 * pad
+    h = np.full((ny, nx), OUTSIDE_DEPTH)
+    h[3 * pad:3 * pad + lv["ny"], 3 * pad:3 * pad + lv["nx"]] = lv["h"]
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[3 * pad:3 * pad + lv["ny"], 3 * pad:3 * pad + lv["nx"]] = 1
+    return dict(nx=nx, ny=ny, parent=lv["parent"], off_i=lv["off_i"] - pad, off_j=lv["off_j"] - pad, h=h, mask=mask)
+
+
+def embed(a, pad3, shape, seed):
+    """a placed at offset pad3 in an array of the given shape filled with noise."""
+    out = np.random.default_rng(seed).uniform(-3.0, 3.0, size=shape)
+    out[pad3:pad3 + a.shape[0], pad3:pad3 + a.shape[1]] = a
+    return out
+
+
+def pin_masked_subrect(lib=None, quick=False):
+    """A masked level whose inside is a rectangle is that rectangular level:
+    the middle level of a 3-level nest grown by 3 parent cells on every side
+    (the new cells outside, 5000 m deep, random state on them) gives bitwise
+    the plain nest's results on every level, from a source and from a random
+    state, with its own child inside it; cells outside hold 0."""
+    sc = scenarios.small_nested(seed=7, nlev=3)
+    pad, p3 = 3, 9
+    tw = masked_twin(sc.levels[1], pad)
+    grand = dict(sc.levels[2], off_i=sc.levels[2]["off_i"] + p3, off_j=sc.levels[2]["off_j"] + p3)
+    twin_levels = [sc.levels[0], tw, grand]
+    assert oracle.validate(twin_levels, sc.dx0, sc.dt) == oracle.OK
+    ox, oy = sc.level_origin(1)
+    w = sc.levels[1]["nx"] * sc.level_dx(1)
+    src = scenarios.Source(ox + 0.3 * w, oy + 0.4 * w, 0.3 * w, 0.2 * w, 0.4, 1.0, scenarios.GAUSS)
+    for mode in ("source", "random"):
+        a = dom(sc.levels, sc.dx0, sc.dt, lib=lib, bc=sc.bc)
+        b = dom(twin_levels, sc.dx0, sc.dt, lib=lib, bc=sc.bc)
+        if mode == "source":
+            a.set_source(*src.astuple())
+            b.set_source(*src.astuple())
+        else:
+            for k, (e, M, N) in enumerate(scenarios.random_state(sc, seed=31, flux=2.0)):
+                z = np.where(sc.levels[k]["h"] > 0, e, sc.levels[k]["h"] + e)
+                a.set_state(k, eta=e, M=M, N=N, zmax=z)
+                if k == 1:
+                    sh = (tw["ny"], tw["nx"])
+                    e, z = embed(e, p3, sh, 1), embed(z, p3, sh, 2)
+                    M = embed(M, p3, (sh[0], sh[1] + 1), 3)
+                    N = embed(N, p3, (sh[0] + 1, sh[1]), 4)
+                b.set_state(k, eta=e, M=M, N=N, zmax=z)
+        n = 80 if quick else 400
+        a.step(n)
+        b.step(n)
+        for k in range(3):
+            ea, Ma, Na = a.get_state(k)
+            eb, Mb, Nb = b.get_state(k)
+            za, zb = a.max_inundation(k), b.max_inundation(k)
+            if k == 1:
+                r = slice(p3, p3 + sc.levels[1]["ny"]), slice(p3, p3 + sc.levels[1]["nx"])
+                out = b.level(1)["mask"] == 0
+                assert np.all(eb[out] == 0.0) and np.all(zb[out] == 0.0), f"{mode}: outside cells changed"
+                eb, zb = eb[r], zb[r]
+                Mb = Mb[r[0], p3:p3 + sc.levels[1]["nx"] + 1]
+                Nb = Nb[p3:p3 + sc.levels[1]["ny"] + 1, r[1]]
+            assert k == 2 or np.abs(Ma).max() > 1e-3, f"{mode}: level {k} at rest"
+            for name, x, y in (("eta", ea, eb), ("M", Ma, Mb), ("N", Na, Nb), ("max", za, zb)):
+                assert np.array_equal(x, y), \
+                    f"masked rectangle, {mode}: level {k} {name} differs by {np.abs(x - y).max():.3e}"
+
+
+def merge_siblings(levels, a, b):
+    """Blocks a < b of one parent merged into one masked level at index a
+    (their children re-parented, with offsets in the merged array)."""
+    A, B = levels[a], levels[b]
+    assert A["parent"] == B["parent"]
+    i0, j0 = min(A["off_i"], B["off_i"]), min(A["off_j"], B["off_j"])
+    i1 = max(A["off_i"] + A["nx"] // 3, B["off_i"] + B["nx"] // 3)
+    j1 = max(A["off_j"] + A["ny"] // 3, B["off_j"] + B["ny"] // 3)
+    nx, ny = 3 * (i1 - i0), 3 * (j1 - j0)
+    h = np.full((ny, nx), OUTSIDE_DEPTH)
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    shift = {}
+    for q, L in ((a, A), (b, B)):
+        di, dj = 3 * (L["off_i"] - i0), 3 * (L["off_j"] - j0)
+        h[dj:dj + L["ny"], di:di + L["nx"]] = L["h"]
+        mask[dj:dj + L["ny"], di:di + L["nx"]] = 1
+        shift[q] = (di, dj)
+    merged = dict(nx=nx, ny=ny, parent=A["parent"], off_i=i0, off_j=j0, h=h, mask=mask)
+    out, where = [], {}
+    for k, L in enumerate(levels):
+        if k == b:
+            continue
+        where[k] = len(out)
+        if k == a:
+            out.append(merged)
+            continue
+        L = dict(L)
+        if L["parent"] in (a, b):
+            di, dj = shift[L["parent"]]
+            L["off_i"], L["off_j"], L["parent"] = L["off_i"] + di, L["off_j"] + dj, a
+        elif L["parent"] >= 0:
+            L["parent"] = where[L["parent"]]
+        out.append(L)
+    return out, shift, where
+
+
+def pin_masked_blocks(lib=None, quick=False):
+    """Two blocks of one resolution held as one masked level (two covered
+    rectangles apart, outside cells between them) give bitwise the results
+    of the two blocks as separate levels, on every level below and above."""
+    sc = scenarios.small_blocks()
+    merged, shift, where = merge_siblings(sc.levels, 1, 2)
+    assert oracle.validate(merged, sc.dx0, sc.dt) == oracle.OK
+    a = dom(sc.levels, sc.dx0, sc.dt, lib=lib, bc=sc.bc)
+    b = dom(merged, sc.dx0, sc.dt, lib=lib, bc=sc.bc)
+    a.set_source(*sc.source.astuple())
+    b.set_source(*sc.source.astuple())
+    n = 60 if quick else 300
+    a.step(n)
+    b.step(n)
+    for k, L in enumerate(sc.levels):
+        got = [*b.get_state(where.get(k, 1)), b.max_inundation(where.get(k, 1))]
+        want = [*a.get_state(k), a.max_inundation(k)]
+        if k in shift:
+            di, dj = shift[k]
+            ny, nx = L["ny"], L["nx"]
+            got = [got[0][dj:dj + ny, di:di + nx], got[1][dj:dj + ny, di:di + nx + 1],
+                   got[2][dj:dj + ny + 1, di:di + nx], got[3][dj:dj + ny, di:di + nx]]
+        for name, x, y in zip(("eta", "M", "N", "max"), want, got):
+            assert np.array_equal(x, y), f"merged blocks: block {k} {name} differs by {np.abs(x - y).max():.3e}"
+    assert np.abs(a.get_state(6)[1]).max() > 1e-3
+
+
+def pin_masked_rest(lib=None, quick=False):
+    """Still water stays still bitwise on an L-shaped level of two touching
+    blocks with a child across their junction, shorelines crossing the
+    exchanges; cells outside hold 0."""
+    sc = scenarios.small_union()
+    rng = np.random.default_rng(13)
+    for lv in sc.levels:
+        h = lv["h"]
+        lv["h"] = np.where(np.abs(h) < 2.0, rng.uniform(-0.02, 0.02, size=h.shape), h)
+    d = dom(sc.levels, sc.dx0, sc.dt, lib=lib, bc=sc.bc)
+    before = [d.get_state(k)[0] for k in range(d.nlev)]
+    d.step(200 if quick else 2000)
+    for k in range(d.nlev):
+        e, M, N = d.get_state(k)
+        assert np.array_equal(e, before[k]) and np.all(M == 0.0) and np.all(N == 0.0), f"L-shaped rest: level {k}"
+    out = oracle.level_mask(sc.levels[1]) == 0
+    assert out.any() and np.all(d.get_state(1)[0][out] == 0.0)
+
+
+def pin_masked_mass(lib=None, quick=False):
+    """Volume is conserved across an L-shaped level of two touching blocks
+    (closed root, random fluxes everywhere): the injected fluxes follow the
+    covered region's boundary, including the inner corner, and carry exactly
+    the parent faces' discharge."""
+    sc = scenarios.small_union()
+    sc.bc = (1, 1, 1, 1)
+    d = dom(sc.levels, sc.dx0, sc.dt, lib=lib, bc=sc.bc, track_clip=True)
+    for k, (e, M, N) in enumerate(scenarios.random_state(sc, seed=24, flux=0.5)):
+        d.set_state(k, eta=e, M=M, N=N)
+    d.bc_root()
+    for k in range(1, d.nlev):
+        d.jnq(k)
+    masks = footprint_masks(sc.levels)
+    v0 = _volume(d, masks)
+    scale = sum(math.fsum(np.abs(d.level(k)["eta"][masks[k]]).ravel().tolist()) * d.dx[k] ** 2
+                for k in range(d.nlev))
+    d.step(100 if quick else 1500)
+    v1 = _volume(d, masks)
+    assert np.abs(d.level(1)["M"]).max() > 0.0
+    assert abs(v1 - v0) <= 1e-12 * scale, f"L-shaped mass drift {abs(v1 - v0) / scale:.3e} (relative)"
+
+
+def pin_masked_symmetry(lib=None, quick=False):
+    """Mirror symmetry across a U-shaped level of three touching blocks:
+    symmetric depth and source give results mirrored to rounding."""
+    dx, dt = 810.0, 1.0
+    npx, npy = 45, 33
+    Xp = (np.arange(npx) + 0.5) * dx
+    Yp = (np.arange(npy) + 0.5) * dx
+    Lx = npx * dx
+
+    def depth(XX, YY):
+        return 90.0 - 110.0 * np.exp(-((XX - Lx / 2) / (0.15 * Lx)) ** 2) + 4.0 * np.cos(YY / 2500.0)
+
+    XX, YY = np.meshgrid(Xp, Yp)
+    child = scenarios.union_level(0, [(12, 9, 21, 4), (12, 13, 6, 8), (27, 13, 6, 8)])
+    Xc = child["off_i"] * dx + (np.arange(child["nx"]) + 0.5) * dx / 3
+    Yc = child["off_j"] * dx + (np.arange(child["ny"]) + 0.5) * dx / 3
+    XC, YC = np.meshgrid(Xc, Yc)
+    child["h"] = np.ascontiguousarray(depth(XC, YC))
+    d = dom([lvl(depth(XX, YY)), child], dx, dt, lib=lib)
+
+    def src(XX, YY):
+        return 1.0 * np.exp(-((XX - Lx / 2) ** 2 + (YY - 0.75 * npy * dx) ** 2) / (2 * (5 * dx) ** 2))
+
+    d.set_eta(0, src(XX, YY))
+    d.set_eta(1, src(XC, YC))
+    d.step(60 if quick else 300)
+    for k in range(2):
+        e, M, N = d.get_state(k)
+        assert np.abs(M).max() > 1e-3
+        assert np.abs(e - e[:, ::-1]).max() <= 1e-9 * max(1.0, np.abs(e).max()), f"U-shaped mirror: level {k} eta"
+        assert np.abs(M + M[:, ::-1]).max() <= 1e-9 * np.abs(M).max(), f"U-shaped mirror: level {k} M"
+        assert np.abs(N - N[:, ::-1]).max() <= 1e-9 * np.abs(N).max(), f"U-shaped mirror: level {k} N"
+
+
+def pin_nest_locality(lib=None, quick=False):
+    """The exchanges touch only the child's edge and ring: a bump in the
+    middle of a child, over a parent at rest, evolves for the first steps
+    (before its stencil reaches the ring blocks) bitwise like the child's
+    grid alone with walls, and the parent stays bitwise at rest.  Run for a
+    rectangular child and for an L-shaped level of touching blocks."""
+    for shaped in (False, True):
+        dx0, dt = 810.0, 0.5
+        root = lvl(np.full((36, 36), 60.0))
+        if shaped:
+            child = scenarios.union_level(0, [(9, 9, 15, 9), (9, 18, 8, 9)])
+            ci, cj = 18, 13                       # the bump's centre, child cells (in the 15x9 block)
+        else:
+            child = dict(nx=45, ny=45, parent=0, off_i=10, off_j=11, h=None)
+            ci, cj = 22, 22
+        ny, nx = child["ny"], child["nx"]
+        jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        child["h"] = np.ascontiguousarray(40.0 + 10.0 * np.sin(ii / 5.0) * np.cos(jj / 7.0))
+        rho = np.hypot(ii - ci, jj - cj) / 4.0
+        bump = np.where(rho < 1.0, np.cos(0.5 * np.pi * rho) ** 2, 0.0)
+        alone_lv = dict(lvl(child["h"]))
+        d = dom([root, child], dx0, dt, lib=lib)
+        a = dom([alone_lv], dx0 / 3.0, dt, lib=lib, bc=(1, 1, 1, 1))
+        d.set_eta(1, bump)
+        a.set_eta(0, np.where(oracle.level_mask(child), bump, 0.0))
+        before = d.get_state(0)
+        for n in range(1, 6):
+            d.step(1)
+            a.step(1)
+            e, M, N = d.get_state(1)
+            ea, Ma, Na = a.get_state(0)
+            inside = oracle.level_mask(child)
+            assert np.array_equal(e[inside], ea[inside]), f"locality ({'L' if shaped else 'rect'}): eta, step {n}"
+            assert np.array_equal(M, Ma) and np.array_equal(N, Na), f"locality ({'L' if shaped else 'rect'}): flux, step {n}"
+            for x, y in zip(d.get_state(0), before):
+                assert np.array_equal(x, y), f"locality: parent moved at step {n}"
+        assert np.abs(M).max() > 1e-3
+
+
+def pin_masked_validation(lib=None, quick=False):
+    """Masks: 0/1, constant over each 3x3 child block, covering something,
+    not on the root; a child keeps 3 cells inside a masked parent; Eq. (4)
+    counts only inside cells."""
+    sc = scenarios.small_union()
+    L = sc.levels
+    assert oracle.validate(L, sc.dx0, sc.dt) == oracle.OK
+    child = dict(L[1], mask=L[1]["mask"].copy())
+    child["mask"][0, 0] = 1 - child["mask"][0, 0]
+    assert oracle.validate([L[0], child, L[2]], sc.dx0, sc.dt) == oracle.ENEST      # not constant over a block
+    child = dict(L[1], mask=np.zeros_like(L[1]["mask"]))
+    assert oracle.validate([L[0], child], sc.dx0, sc.dt) == oracle.ENEST            # covers nothing
+    root = dict(L[0], mask=np.ones((L[0]["ny"], L[0]["nx"]), dtype=np.uint8))
+    assert oracle.validate([root] + L[1:], sc.dx0, sc.dt) == oracle.ENEST          # mask on the root
+    assert oracle.validate([L[0], L[1], dict(L[2], off_i=15)], sc.dx0, sc.dt) == oracle.OK      # 3 cells of margin
+    assert oracle.validate([L[0], L[1], dict(L[2], off_i=16)], sc.dx0, sc.dt) == oracle.ENEST   # 2 cells of margin
+    deep = dict(L[1], h=np.where(L[1]["mask"] != 0, L[1]["h"], OUTSIDE_DEPTH))
+    assert oracle.validate([L[0], deep, L[2]], sc.dx0, sc.dt) == oracle.OK
+
+
+# ---------------------------------------------------------------------------
 def cbrt_hard_cases(n, seed):
     """Inputs whose cube root lies within about 2^-106 of a midpoint between
     two adjacent doubles, with the correctly rounded roots: for y < y' adjacent
@@ -654,4 +929,6 @@ def pin_source(lib=None, quick=False):
 
 ALL = [pin_cbrt_rn, pin_source, pin_lake_at_rest, pin_closed_mass, pin_nested_mass, pin_dispersion, pin_standing_period,
        pin_wave_speed, pin_mirror_symmetry, pin_nested_symmetry, pin_friction_ode, pin_consistency,
-       pin_dam_break, pin_max_tracking, pin_jnz_linear, pin_open_boundary, pin_validation]
+       pin_dam_break, pin_max_tracking, pin_jnz_linear, pin_open_boundary, pin_validation, pin_masked_subrect,
+       pin_masked_blocks, pin_masked_rest, pin_masked_mass, pin_masked_symmetry, pin_masked_validation,
+       pin_nest_locality]

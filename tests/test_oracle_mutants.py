@@ -57,11 +57,22 @@ MUTANTS = {
         "if (C->h[CELL(C, ii, jj)] + e > d->eps) { s += e; k++; }", "{ s += e; k++; }"),
     "child->parent: two columns summed": (
         "for (int ii = 3 * I; ii < 3 * I + 3; ii++)", "for (int ii = 3 * I; ii < 3 * I + 2; ii++)"),
-    "parent->child: east face index": (
-        "C->M[XF(C, C->nx, jf)] = P->M[XF(P, I0 + fw, J0 + jf / 3)];",
-        "C->M[XF(C, C->nx, jf)] = P->M[XF(P, I0 + fw - 1, J0 + jf / 3)];"),
-    "parent->child: south row": (
-        "C->N[YF(C, i, 0)] = P->N[YF(P, I0 + i / 3, J0)];", "C->N[YF(C, i, 0)] = P->N[YF(P, I0 + i / 3, J0 + 1)];"),
+    "parent->child: x-face of the cell to the west": (
+        "C->M[XF(C, 3 * I, 3 * J + k)] = P->M[XF(P, I0 + I, J0 + J)];",
+        "C->M[XF(C, 3 * I, 3 * J + k)] = P->M[XF(P, I0 + I - 1, J0 + J)];"),
+    "parent->child: y-face one row up": (
+        "C->N[YF(C, 3 * I + k, 3 * J)] = P->N[YF(P, I0 + I, J0 + J)];",
+        "C->N[YF(C, 3 * I + k, 3 * J)] = P->N[YF(P, I0 + I, J0 + J + 1)];"),
+    "parent->child: faces inside the footprint injected too": (
+        "if (covered(C, I - 1, J) != covered(C, I, J))", "if (covered(C, I - 1, J) || covered(C, I, J))"),
+    "parent->child: child rows of a face": (
+        "C->M[XF(C, 3 * I, 3 * J + k)]", "C->M[XF(C, 3 * I, 3 * J + k / 2)]"),
+    "mask: faces to outside cells active": (
+        "    if (!inside(L, i - 1, j) || !inside(L, i, j)) return 0;\n", ""),
+    "mask: outside cells updated": ("            if (!inside(L, i, j)) continue;\n            double e", "            double e"),
+    "child->parent: ring of the rectangle, not of the covered region": (
+        "if (!covered(C, I + di, J + dj)) ring = 1;",
+        "if (I + di < 0 || J + dj < 0 || I + di >= fw || J + dj >= fh) ring = 1;"),
     "open boundary: west sign": (
         "radiate(d, L->h[CELL(L, 0, j)], L->eta[CELL(L, 0, j)], -1.0);",
         "radiate(d, L->h[CELL(L, 0, j)], L->eta[CELL(L, 0, j)], 1.0);"),
@@ -70,7 +81,8 @@ MUTANTS = {
 
 BATTERY = [pins.pin_cbrt_rn, pins.pin_source, pins.pin_lake_at_rest, pins.pin_closed_mass, pins.pin_nested_mass, pins.pin_jnz_linear,
            pins.pin_max_tracking, pins.pin_open_boundary, pins.pin_dispersion, pins.pin_mirror_symmetry,
-           pins.pin_friction_ode, pins.pin_dam_break, pins.pin_consistency]
+           pins.pin_friction_ode, pins.pin_dam_break, pins.pin_consistency, pins.pin_masked_subrect,
+           pins.pin_masked_blocks, pins.pin_masked_mass, pins.pin_nest_locality]
 
 
 def test_unmodified_copy_passes(tmp_path):
