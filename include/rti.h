@@ -78,19 +78,36 @@ enum { RTI_GAUSS = 0, RTI_COS2_ELLIPSE = 1 };
                                        workgroup per tile (also a flag of rti_batch_create) */
 #define RTI_MAX_LEVELS 128
 
-/* One nest level (a rectangular block of one resolution: a resolution that
- * the paper's model covers with several blocks, Table 1, is several entries
- * here, each with its own parent).  Level 0 is the root (parent = -1); every
- * other level names a parent listed before it.  A child's spacing is its parent's divided by 3
- * (Sec. II-A); its nx and ny are multiples of 3 and at least 9; its footprint,
- * the parent cells [off_i, off_i + nx/3) x [off_j, off_j + ny/3), lies inside
- * the parent with at least 3 parent cells on every side; sibling footprints
- * keep 3 parent cells apart. */
+/* One nest level.  A resolution that the paper's model covers with several
+ * rectangular blocks (Sec. II-A, Table 1) is given either as several entries,
+ * one per block, each with its own parent, or -- where blocks of the
+ * resolution touch -- as one entry whose array covers their bounding box with
+ * a mask of the cells inside the blocks.  Level 0 is the root (parent = -1);
+ * every other level names a parent listed before it.  A child's spacing is
+ * its parent's divided by 3 (Sec. II-A); its nx and ny are multiples of 3 and
+ * at least 9; its footprint, the parent cells [off_i, off_i + nx/3) x
+ * [off_j, off_j + ny/3), lies inside the parent with at least 3 parent cells
+ * on every side; sibling footprints keep 3 parent cells apart.
+ *
+ * Masked levels (mask not NULL; not on the root): mask[i + nx*j] is 1 for a
+ * cell inside the level and 0 for one outside; it is constant over the 3x3
+ * cells of each parent cell, so each parent cell of the footprint is covered
+ * (its cells inside) or not, and at least one is covered.  Blocks that share
+ * an edge are then one grid: their common faces are computed like any other.
+ * Cells outside take no part in the step: every face touching one carries no
+ * computed flux, the parent's flux is injected on every parent face between a
+ * covered and an uncovered parent cell (Sec. IV-A), and the child-to-parent
+ * mean (Sec. IV-C) is taken on every covered parent cell with an uncovered
+ * neighbour (8-neighbourhood; for a rectangle, its outermost ring).  A child
+ * of a masked level keeps 3 of its parent cells away from the cells outside
+ * it.  h and the values given for outside cells are ignored; the state and
+ * the maxima read back 0 there. */
 typedef struct {
     int32_t nx, ny;        /* cells */
     int32_t parent;        /* index into levels[], -1 for the root */
     int32_t off_i, off_j;  /* child origin in parent cells */
     const double *h;       /* host, nx*ny still-water depth [m]; copied by rti_domain_create */
+    const uint8_t *mask;   /* host, nx*ny, 1 inside / 0 outside, or NULL (every cell); copied by create */
 } rti_level_desc;
 
 typedef struct {

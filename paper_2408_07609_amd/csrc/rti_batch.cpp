@@ -185,11 +185,24 @@ int build_tables(rti_batch *B)
     return RTI_OK;
 }
 
+// The boundary fluxes of the members' masked children (after the fused launch).
+hipError_t launch_member_injects(rti_batch *B, int flip, hipStream_t s)
+{
+    for (size_t m = 0; m < B->members.size(); ++m) {
+        const rti_domain *D = B->members[m];
+        if (D->dev.ninject == 0) continue;
+        const hipError_t e = launch_inject(D->dev, B->par[m] ^ flip, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 int launch_batch_step(rti_batch *B, int flip, hipStream_t s)
 {
     HIP_TRY(launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, B->bulk32, s));
     HIP_TRY(launch_fused_batch(B->dev, flip, B->bulk32,
                                fused_grid(B->dev.ntiles, (B->flags & RTI_FLAG_PERSISTENT) != 0, B->cu_count), s));
+    HIP_TRY(launch_member_injects(B, flip, s));
     return RTI_OK;
 }
 
@@ -223,9 +236,7 @@ void advance(rti_batch *B, int64_t n)
     for (rti_domain *D : B->members) {
         D->steps += n;
         D->cur ^= (int)(n & 1);
-        int64_t cells = 0;
-        for (const auto &p : D->plan.lv) cells += (int64_t)p.nx * p.ny;
-        B->cell_updates_all += cells * n;
+        B->cell_updates_all += D->plan.cells * n;
     }
     B->steps += n;
 }
@@ -400,6 +411,7 @@ int rti_batch_profile(rti_batch *B, int64_t nsteps, double *fused_ms, double *ac
                 e = launch_active_batch(B->dev, flip, (B->flags & RTI_FLAG_NO_ACTIVE) ? 1 : 0, B->bulk32, B->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[1], B->stream);
             if (e == hipSuccess) e = launch_fused_batch(B->dev, flip, B->bulk32, grid, B->stream);
+            if (e == hipSuccess) e = launch_member_injects(B, flip, B->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[2], B->stream);
             if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
             float ta = 0.0f, tf = 0.0f;

@@ -213,7 +213,9 @@ __device__ void ring_mean(const DomainDev &d, int b, int e)
 
 // The new parent flux on a child's edge goes to the 3 child faces it covers.
 // cmask: bit q set when child q's edge faces may lie in the tile's output
-// rows and columns (children from the 33rd on are always visited).
+// rows and columns (children from the 33rd on are always visited).  A masked
+// child's boundary is injected after the launch from its list (k_inject): the
+// child's own tiles write its faces inside the rectangle in this launch.
 template <typename F>
 __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c, int r, bool xface, bool yface,
                              F Mnew, F Nnew, unsigned cmask)
@@ -221,6 +223,7 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
     for (int q = 0; q < L.n_children; ++q) {
         if (q < 32 && !((cmask >> q) & 1u)) continue;
         const LevelDev &C = level_of(d, child_level(d, L.first_child + q));
+        if (C.masked) continue;
         const int fw = C.nx / 3, fh = C.ny / 3;
         const int CP = C.pitch;
         if (xface && r >= C.off_j && r < C.off_j + fh && (c == C.off_i || c == C.off_i + fw)) {

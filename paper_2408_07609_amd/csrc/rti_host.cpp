@@ -31,6 +31,26 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+// Does child level C cover parent cell (I, J) of its footprint (counted from
+// its origin)?  A rectangular child covers its whole footprint.
+bool covers(const LevelPlan &C, int I, int J)
+{
+    const int fw = C.nx / 3, fh = C.ny / 3;
+    if (I < 0 || J < 0 || I >= fw || J >= fh) return false;
+    return C.cover.empty() || C.cover[(size_t)I + (size_t)fw * J] != 0;
+}
+
+// A ring cell of child C (Sec. IV-C): a covered parent cell with an uncovered
+// one among its 8 neighbours (the outermost ring of a rectangle, corners once).
+bool ring_cell(const LevelPlan &C, int I, int J)
+{
+    if (!covers(C, I, J)) return false;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di)
+            if (!covers(C, I + di, J + dj)) return true;
+    return false;
+}
+
 // Static bits and coupled tiles of every tile.
 //
 // A tile's extended region (its cells plus the 2-cell halo its stencil reads,
@@ -103,7 +123,17 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                 uint32_t cmask = 0;
                 int q = 0;   // index of the next child among the level's children (increasing level order)
                 deps.clear();
-                if (ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4) {
+                bool near_edge = ax <= 3 || bx >= p.nx - 4 || ay <= 3 || by >= p.ny - 4;
+                if (l > 0 && !near_edge && !p.cover.empty()) {
+                    // a masked level's boundary inside the rectangle is injected too: an
+                    // uncovered parent cell next to the read region's parent cells
+                    const int I0 = std::max(rx0, 0) / 3 - 1, I1 = std::min(rx1, p.nx - 1) / 3 + 1;
+                    const int J0 = std::max(ry0, 0) / 3 - 1, J1 = std::min(ry1, p.ny - 1) / 3 + 1;
+                    for (int J = J0; J <= J1 && !near_edge; ++J)
+                        for (int I = I0; I <= I1 && !near_edge; ++I)
+                            if (!covers(p, I, J)) near_edge = true;
+                }
+                if (near_edge) {
                     bits |= TI_EDGE;
                     if (l > 0) {
                         // parent cells over the read region (edge faces i = nx map to parent face off_i + nx/3),
@@ -119,6 +149,22 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                     if (C.parent != l) continue;
                     const int fx0 = C.off_i, fx1 = C.off_i + C.nx / 3 - 1;   // footprint, inclusive
                     const int fy0 = C.off_j, fy1 = C.off_j + C.ny / 3 - 1;
+                    if (!C.cover.empty()) {
+                        // masked child: its edges are injected by k_inject (no cmask bit); the
+                        // tile reads ring means where a ring cell lies in its extended region,
+                        // and depends on the child tiles of the ring blocks in its read region
+                        ++q;
+                        const int a = std::max(rx0, fx0), b = std::min(rx1, fx1);
+                        const int c = std::max(ry0, fy0), e = std::min(ry1, fy1);
+                        for (int t = c; t <= e; ++t)
+                            for (int u = a; u <= b; ++u) {
+                                const int I = u - fx0, J = t - fy0;
+                                if (!ring_cell(C, I, J)) continue;
+                                if (u >= ax && u <= bx && t >= ay && t <= by) bits |= TI_CHILD;
+                                add_rect(k, 3 * I, 3 * I + 3, 3 * J, 3 * J + 3);
+                            }
+                        continue;
+                    }
                     {
                         // output columns x0 .. x0+59, rows y0 .. y0+th-1: does an edge face of child k lie there?
                         const int ox0 = tx * RTI_TW, ox1 = ox0 + RTI_TW - 1, oy0 = ty * th, oy1 = oy0 + th - 1;
@@ -159,7 +205,14 @@ void plan_tiles(Plan &plan, int th, size_t dep_cap)
                 plan.tcmask[g] = cmask;
                 plan.tlev[g] = (uint8_t)l;
                 const int w = std::min(RTI_TW, p.nx - tx * RTI_TW), hgt = std::min(th, p.ny - ty * th);
-                plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
+                if (p.inside.empty()) {
+                    plan.tcells[g] = std::max(0, w) * std::max(0, hgt);
+                } else {
+                    int n = 0;
+                    for (int j = ty * th; j < ty * th + hgt; ++j)
+                        for (int i = tx * RTI_TW; i < tx * RTI_TW + w; ++i) n += p.inside[(size_t)i + (size_t)p.nx * j];
+                    plan.tcells[g] = n;
+                }
                 plan.dep_off[(size_t)g + 1] = (int32_t)plan.dep.size();
             }
         }
@@ -186,6 +239,25 @@ static_assert(RTI_TH == RTI_TILE_ROWS_DEFAULT && RTI_TH_MIN == RTI_TILE_ROWS_MIN
               "tile heights of the ABI and the kernels disagree");
 
 namespace {
+
+// Cells whose (2r+1) x (2r+1) neighbourhood lies inside the grid and inside
+// `in` (an nx x ny 0/1 map).
+std::vector<uint8_t> erode(const std::vector<uint8_t> &in, int nx, int ny, int r)
+{
+    std::vector<uint8_t> rows(in.size(), 0), out(in.size(), 0);
+    std::vector<int> pre((size_t)std::max(nx, ny) + 1);
+    for (int j = 0; j < ny; ++j) {
+        pre[0] = 0;
+        for (int i = 0; i < nx; ++i) pre[i + 1] = pre[i] + (in[(size_t)i + (size_t)nx * j] != 0);
+        for (int i = r; i + r < nx; ++i) rows[(size_t)i + (size_t)nx * j] = (pre[i + r + 1] - pre[i - r] == 2 * r + 1);
+    }
+    for (int i = 0; i < nx; ++i) {
+        pre[0] = 0;
+        for (int j = 0; j < ny; ++j) pre[j + 1] = pre[j] + rows[(size_t)i + (size_t)nx * j];
+        for (int j = r; j + r < ny; ++j) out[(size_t)i + (size_t)nx * j] = (pre[j + r + 1] - pre[j - r] == 2 * r + 1);
+    }
+    return out;
+}
 
 // Validate the descriptor and lay the domain out in device memory.
 int plan_domain(const rti_domain_desc *d, Plan &plan)
@@ -229,6 +301,32 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
             p.ox = P.ox + (double)L.off_i * P.dx;
             p.oy = P.oy + (double)L.off_j * P.dx;
         }
+        p.cells = (int64_t)L.nx * L.ny;
+        if (L.mask) {
+            // touching blocks of one resolution held as one level (Sec. II-A, Table 1)
+            if (k == 0) return fail(RTI_ENEST, "level 0 (the root) cannot have a mask");
+            const int fw = L.nx / 3, fh = L.ny / 3;
+            p.inside.assign((size_t)L.nx * L.ny, 0);
+            p.cover.assign((size_t)fw * fh, 0);
+            int64_t covered = 0;
+            for (int J = 0; J < fh; ++J)
+                for (int I = 0; I < fw; ++I) {
+                    const uint8_t v = L.mask[(size_t)3 * I + (size_t)L.nx * (3 * J)];
+                    if (v > 1) return fail(RTI_EINVAL, "level %d: mask values must be 0 or 1", k);
+                    for (int jj = 3 * J; jj < 3 * J + 3; ++jj)
+                        for (int ii = 3 * I; ii < 3 * I + 3; ++ii) {
+                            const size_t c = (size_t)ii + (size_t)L.nx * jj;
+                            if (L.mask[c] != v)
+                                return fail(RTI_ENEST, "level %d: mask not constant over the 3x3 cells of parent cell (%d, %d)",
+                                            k, L.off_i + I, L.off_j + J);
+                            p.inside[c] = v;
+                        }
+                    p.cover[(size_t)I + (size_t)fw * J] = v;
+                    covered += v;
+                }
+            if (covered == 0) return fail(RTI_ENEST, "level %d: the mask covers no parent cell", k);
+            p.cells = 9 * covered;
+        }
         // Zero-padded layout (see LevelDev): pitch >= nx + 64, RTI_PAD_BOTTOM + ny + RTI_PAD_TOP rows.
         const long long rows = (long long)RTI_PAD_BOTTOM + L.ny + RTI_PAD_TOP;
         const long long pitch = (long long)align_up((size_t)L.nx + 64, 32);
@@ -248,12 +346,32 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
             if (!apart) return fail(RTI_ENEST, "levels %d and %d: sibling footprints closer than 3 parent cells", a, b);
         }
     }
-    // Eq. (4): dx / dt >= sqrt(2 g h_max) on every level.
+    // A child of a masked level keeps 3 parent cells away from the cells outside it.
+    {
+        std::vector<std::vector<uint8_t>> core(d->n_levels);
+        for (int k = 1; k < d->n_levels; ++k) {
+            const LevelPlan &C = plan.lv[k];
+            const LevelPlan &P = plan.lv[C.parent];
+            if (P.inside.empty()) continue;
+            std::vector<uint8_t> &pc = core[C.parent];
+            if (pc.empty()) pc = erode(P.inside, P.nx, P.ny, 3);
+            for (int J = 0; J < C.ny / 3; ++J)
+                for (int I = 0; I < C.nx / 3; ++I)
+                    if (covers(C, I, J) && !pc[(size_t)(C.off_i + I) + (size_t)P.nx * (C.off_j + J)])
+                        return fail(RTI_ENEST, "level %d: parent cell (%d, %d) it covers lies within 3 cells of a cell "
+                                    "outside its masked parent %d", k, C.off_i + I, C.off_j + J, C.parent);
+        }
+    }
+    // Eq. (4): dx / dt >= sqrt(2 g h_max) on every level (over the cells inside it).
+    plan.cells = 0;
     for (int k = 0; k < d->n_levels; ++k) {
         const rti_level_desc &L = d->levels[k];
+        const std::vector<uint8_t> &in = plan.lv[k].inside;
+        plan.cells += plan.lv[k].cells;
         double hmax = 0.0;
         const size_t n = (size_t)L.nx * (size_t)L.ny;
         for (size_t c = 0; c < n; ++c) {
+            if (!in.empty() && !in[c]) continue;
             const double h = L.h[c];
             if (!std::isfinite(h)) return fail(RTI_EINVAL, "level %d: non-finite depth at cell %zu", k, c);
             hmax = std::max(hmax, h);
@@ -274,26 +392,48 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
         bytes += 2 * p.eta_bytes + 2 * p.cells_bytes + 2 * p.xf_bytes + 2 * p.yf_bytes;
     }
     plan.level_bytes = bytes;
-    // Ring cells of every child (its footprint's outermost ring of parent cells, Sec. IV-C), and
-    // one ring-mean array, laid out like eta, per level with children.
+    // Ring cells of every child (Sec. IV-C: covered parent cells next to an uncovered one; the
+    // outermost ring of a rectangular footprint), and one ring-mean array, laid out like eta, per
+    // level with children.  The boundary faces of every masked child: parent faces between a
+    // covered and an uncovered parent cell, whose flux the child's 3 faces there receive.
     plan.ring.clear();
+    plan.inject.clear();
     plan.ring_bytes = 0;
     std::vector<char> has_children(plan.lv.size(), 0);
     for (int k = 1; k < (int)plan.lv.size(); ++k) {
         const LevelPlan &C = plan.lv[k];
+        const LevelPlan &P = plan.lv[C.parent];
         const int fw = C.nx / 3, fh = C.ny / 3;
         if (fw > 65535 || fh > 32767) return fail(RTI_EINVAL, "level %d: footprint %d x %d too large", k, fw, fh);
         has_children[C.parent] = 1;
         for (int J = 0; J < fh; ++J)
             for (int I = 0; I < fw; ++I)
-                if (I == 0 || I == fw - 1 || J == 0 || J == fh - 1) {
+                if (ring_cell(C, I, J)) {
                     plan.ring.push_back(k | (C.parent << 16));
                     plan.ring.push_back((J << 16) | I);
+                }
+        if (C.cover.empty()) continue;
+        for (int J = 0; J < fh; ++J)             // x-faces between parent cells (I-1, J) and (I, J)
+            for (int I = 0; I <= fw; ++I)
+                if (covers(C, I - 1, J) != covers(C, I, J)) {
+                    plan.inject.push_back(k | (C.parent << 16));
+                    plan.inject.push_back(0);
+                    plan.inject.push_back(3 * I + C.pitch * (3 * J));
+                    plan.inject.push_back((C.off_i + I) + P.pitch * (C.off_j + J));
+                }
+        for (int J = 0; J <= fh; ++J)            // y-faces between parent cells (I, J-1) and (I, J)
+            for (int I = 0; I < fw; ++I)
+                if (covers(C, I, J - 1) != covers(C, I, J)) {
+                    plan.inject.push_back(k | (C.parent << 16));
+                    plan.inject.push_back(1);
+                    plan.inject.push_back(3 * I + C.pitch * (3 * J));
+                    plan.inject.push_back((C.off_i + I) + P.pitch * (C.off_j + J));
                 }
     }
     for (int l = 0; l < (int)plan.lv.size(); ++l)
         if (has_children[l]) plan.ring_bytes += plan.lv[l].eta_bytes;
-    bytes += plan.ring_bytes + align_up(sizeof(int32_t) * std::max<size_t>(plan.ring.size(), 1), kAlign);
+    bytes += plan.ring_bytes + align_up(sizeof(int32_t) * std::max<size_t>(plan.ring.size(), 1), kAlign)
+             + align_up(sizeof(int32_t) * std::max<size_t>(plan.inject.size(), 4), kAlign);
     plan.slev.clear();
     for (int k = 0; k < (int)plan.lv.size(); ++k)
         plan.slev.insert(plan.slev.end(), (size_t)plan.lv[k].s_tiles_x * plan.lv[k].s_tiles_y, (uint8_t)k);
@@ -357,6 +497,10 @@ int carve(rti_domain *D)
     D->ring_dev = reinterpret_cast<int32_t *>(take(align_up(sizeof(int32_t) * std::max<size_t>(D->plan.ring.size(), 1), kAlign)));
     D->dev.ring_cells = D->ring_dev;
     D->dev.nring = (int32_t)(D->plan.ring.size() / 2);
+    D->inject_dev = reinterpret_cast<int32_t *>(
+        take(align_up(sizeof(int32_t) * std::max<size_t>(D->plan.inject.size(), 4), kAlign)));
+    D->dev.inject = D->inject_dev;
+    D->dev.ninject = (int32_t)(D->plan.inject.size() / 4);
     const size_t nt = (size_t)D->plan.ntiles_cap;
     D->tinfo = reinterpret_cast<uint8_t *>(take(align_up(nt, kAlign)));
     D->dev.tinfo = D->tinfo;
@@ -545,6 +689,7 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
         HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s,
                              all));
     }
+    HIP_TRY(launch_inject(D->dev, b, s));
     return RTI_OK;
 }
 
@@ -552,10 +697,8 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
 int active_cells(rti_domain *D, int64_t *tiles, int64_t *cells)
 {
     if (D->flags & RTI_FLAG_PHASED) {
-        int64_t n = 0;
-        for (const auto &p : D->plan.lv) n += (int64_t)p.nx * p.ny;
         *tiles = D->dev.s_ntiles;
-        *cells = n;
+        *cells = D->plan.cells;
         return RTI_OK;
     }
     int n = 0;
@@ -812,6 +955,7 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
             sbase += p.s_tiles_x * p.s_tiles_y;
             L.r = desc->dt / p.dx;
             L.gr = desc->g * L.r;
+            L.masked = p.inside.empty() ? 0 : 1;
         }
         {
             int nc = 0;
@@ -847,6 +991,9 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         if (e == hipSuccess && !plan.ring.empty())
             e = hipMemcpyAsync(D->ring_dev, plan.ring.data(), sizeof(int32_t) * plan.ring.size(), hipMemcpyHostToDevice,
                                D->stream);
+        if (e == hipSuccess && !plan.inject.empty())
+            e = hipMemcpyAsync(D->inject_dev, plan.inject.data(), sizeof(int32_t) * plan.inject.size(),
+                               hipMemcpyHostToDevice, D->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(D->stream);
         if (e != hipSuccess) {
             rti_domain_destroy(D);
@@ -854,7 +1001,19 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         }
         for (int k = 0; k < dv.nlev; ++k) {
             const LevelPlan &p = plan.lv[k];
-            rc = put_rows_b(D, D->lvh[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
+            if (p.inside.empty()) {
+                rc = put_rows_b(D, D->lvh[k].h, p.pitch, desc->levels[k].h, p.nx, p.ny);
+            } else {
+                // cells outside a masked level: dry ground far above the sea (kOutsideDepth)
+                std::vector<double> h(desc->levels[k].h, desc->levels[k].h + (size_t)p.nx * p.ny);
+                for (size_t c = 0; c < h.size(); ++c)
+                    if (!p.inside[c]) h[c] = kOutsideDepth;
+                rc = put_rows_b(D, D->lvh[k].h, p.pitch, h.data(), p.nx, p.ny);
+                if (!rc) {
+                    e = hipStreamSynchronize(D->stream);
+                    if (e != hipSuccess) rc = fail(RTI_EHIP, "uploading the depth failed: %s", hipGetErrorString(e));
+                }
+            }
             if (rc) { rti_domain_destroy(D); return rc; }
             // the lake at rest on the depth as the kernels see it (rounded to FP32 in FP32-bulk)
             rc = device_initial(D, k, nullptr);
@@ -1019,6 +1178,14 @@ int rti_run(rti_domain *D, double t_end)
     return check_status(D);
 }
 
+// Cells outside a masked level read back as 0.
+static void zero_outside(const LevelPlan &p, double *a)
+{
+    if (!a || p.inside.empty()) return;
+    for (size_t c = 0; c < p.inside.size(); ++c)
+        if (!p.inside[c]) a[c] = 0.0;
+}
+
 int rti_max_inundation(rti_domain *D, int32_t level, double *out)
 {
     int rc = check_level(D, level);
@@ -1028,6 +1195,7 @@ int rti_max_inundation(rti_domain *D, int32_t level, double *out)
     rc = get_rows_b(D, out, p.nx, D->lvh[level].zmax, p.pitch, p.ny);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
+    zero_outside(p, out);
     return RTI_OK;
 }
 
@@ -1041,6 +1209,7 @@ int rti_get_state(rti_domain *D, int32_t level, double *eta, double *M, double *
     if (M && (rc = get_rows_b(D, M, p.nx + 1, L.M[D->cur], p.pitch, p.ny))) return rc;
     if (N && (rc = get_rows_b(D, N, p.nx, L.N[D->cur], p.pitch, p.ny + 1))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
+    zero_outside(p, eta);
     return RTI_OK;
 }
 
@@ -1050,6 +1219,15 @@ int rti_set_state(rti_domain *D, int32_t level, const double *eta, const double 
     if (rc) return rc;
     const LevelPlan &p = D->plan.lv[level];
     const LevelDev &L = D->lvh[level];
+    std::vector<double> own;
+    if (eta && !p.inside.empty()) {
+        // cells outside keep the level of their ground (-kOutsideDepth as the device stores it)
+        const double out = (D->plan.elem == sizeof(float)) ? -(double)(float)kOutsideDepth : -kOutsideDepth;
+        own.assign(eta, eta + (size_t)p.nx * p.ny);
+        for (size_t c = 0; c < own.size(); ++c)
+            if (!p.inside[c]) own[c] = out;
+        eta = own.data();
+    }
     for (int b = 0; b < 2; ++b) {
         if (eta && (rc = put_rows(D, L.eta[b], p.pitch, eta, p.nx, p.ny))) return rc;
         if (M && (rc = put_rows_b(D, L.M[b], p.pitch, M, p.nx + 1, p.ny))) return rc;
@@ -1067,6 +1245,12 @@ int rti_set_max(rti_domain *D, int32_t level, const double *zmax)
     if (rc) return rc;
     if (!zmax) return fail(RTI_EINVAL, "zmax is NULL");
     const LevelPlan &p = D->plan.lv[level];
+    std::vector<double> own;
+    if (!p.inside.empty()) {
+        own.assign(zmax, zmax + (size_t)p.nx * p.ny);
+        zero_outside(p, own.data());
+        zmax = own.data();
+    }
     if ((rc = put_rows_b(D, D->lvh[level].zmax, p.pitch, zmax, p.nx, p.ny))) return rc;
     if ((rc = forget_quiet(D))) return rc;
     HIP_TRY(hipStreamSynchronize(D->stream));
@@ -1106,6 +1290,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
             if (e == hipSuccess) e = launch_momentum(D->dev, b, D->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[3], D->stream);
             if (e == hipSuccess) e = launch_jnq(D->dev, b, D->stream);
+            if (e == hipSuccess) e = launch_inject(D->dev, b, D->stream);   // masked children (timed as k_jnq)
             if (e == hipSuccess) e = hipEventRecord(ev[4], D->stream);
             kinds[0] = K_MASS; kinds[1] = K_JNZ; kinds[2] = K_MOMENTUM; kinds[3] = K_JNQ;
             nk = 4;
@@ -1115,6 +1300,7 @@ int rti_profile(rti_domain *D, int64_t nsteps, double *ms, const char **names, i
             if (e == hipSuccess)
                 e = launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count),
                                  D->stream, (D->flags & RTI_FLAG_NO_ACTIVE) != 0);
+            if (e == hipSuccess) e = launch_inject(D->dev, b, D->stream);   // masked children (timed with k_fused)
             if (e == hipSuccess) e = hipEventRecord(ev[2], D->stream);
             kinds[0] = K_ACTIVE; kinds[1] = K_FUSED;
             nk = 2;
@@ -1179,8 +1365,7 @@ int cells_done(rti_domain *D, unsigned long long *out)
 int rti_cell_updates(rti_domain *D, int64_t *all, int64_t *computed)
 {
     if (!D || !all || !computed) return fail(RTI_EINVAL, "NULL argument");
-    int64_t cells = 0;
-    for (const auto &p : D->plan.lv) cells += (int64_t)p.nx * p.ny;
+    const int64_t cells = D->plan.cells;
     unsigned long long done = 0;
     int rc = cells_done(D, &done);
     if (rc) return rc;

@@ -80,6 +80,9 @@ struct LevelDev {
     int32_t tiles_x, tiles_y, tile_base;   // tile grid of the fused kernel and its first global tile
     int32_t s_tiles_x, s_tile_base;        // 64x4 tile grid of the per-phase kernels
     int32_t first_child, n_children;       // children are levels first_child .. (listed in child[])
+    int32_t masked;                        // 1: some cells of the rectangle are outside the level (touching
+                                           // blocks held as one level); its edge fluxes come from the
+                                           // injection list (DomainDev::inject), not from inject_edges
     double r, gr;                          // dt/dx and g*dt/dx
     double *eta[2];
     void *h, *zmax, *M[2], *N[2];          // element type: double, or float when bulk32
@@ -118,6 +121,9 @@ struct DomainDev {
     const uint32_t *tcmask;                // ntiles: bit q = child q of the tile's level has edge faces in its output
     int32_t nring;                         // ring cells of all children
     const int32_t *ring_cells;             // nring x 2: child level | parent level << 16, (J << 16) | I of ring cell (I, J)
+    int32_t ninject;                       // parent faces on the boundary of masked children
+    const int32_t *inject;                 // ninject x 4: child level | parent level << 16, 0 (x-face) or 1 (y-face),
+                                           // element offset of the first of the 3 child faces, of the parent face
 };
 
 // Reads of the level table and the per-tile level indices go through the
@@ -172,6 +178,9 @@ hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnz(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_momentum(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s);
+// The new parent fluxes on the boundary of masked children (DomainDev::inject),
+// after the step's momentum: buffer b^1 of the parent into buffer b^1 of the child.
+hipError_t launch_inject(const DomainDev &d, int b, hipStream_t s);
 hipError_t launch_finite_check(const DomainDev &d, int b, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_init_level(const LevelDev &L, int bulk32, const InitSource &sp, hipStream_t s);

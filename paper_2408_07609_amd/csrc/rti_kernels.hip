@@ -132,28 +132,18 @@ __global__ __launch_bounds__(256) void k_mass(DomainDev d, int b)
     L.eta[b ^ 1][c] = e;
 }
 
-// Child -> parent (Sec. IV-C): each parent cell on the ring of the child's
-// footprint := max(mean of the wet 3x3 child cells (summed j outer, i inner),
-// parent ground); unchanged when none is wet.  blockIdx.y = child level - 1.
+// Child -> parent (Sec. IV-C): each parent cell on the ring of a child's
+// footprint (DomainDev::ring_cells, one thread each) := max(mean of the wet
+// 3x3 child cells (summed j outer, i inner), parent ground); unchanged when
+// none is wet.
 __global__ __launch_bounds__(256) void k_jnz(DomainDev d, int b)
 {
-    const int c = blockIdx.y + 1;
-    const LevelDev &C = level_of(d, c);
-    const LevelDev &Pl = level_of(d, C.parent);
-    const int fw = C.nx / 3, fh = C.ny / 3;
-    const int ring = 2 * fw + 2 * (fh - 2);
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ring) return;
-    int I, J;
-    if (k < fw) {
-        I = k; J = 0;
-    } else if (k < 2 * fw) {
-        I = k - fw; J = fh - 1;
-    } else {
-        const int q = k - 2 * fw;
-        J = 1 + (q >> 1);
-        I = (q & 1) ? fw - 1 : 0;
-    }
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d.nring) return;
+    const int kp = d.ring_cells[2 * e], ij = d.ring_cells[2 * e + 1];
+    const int I = ij & 0xffff, J = ij >> 16;
+    const LevelDev &C = d.lv[kp & 0xffff];
+    const LevelDev &Pl = d.lv[kp >> 16];
     const double *ce = C.eta[b ^ 1];
     const double *ch = static_cast<const double *>(C.h);
     const int CP = C.pitch;
@@ -213,6 +203,7 @@ __global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
 {
     const int c = blockIdx.y + 1;
     const LevelDev &C = level_of(d, c);
+    if (C.masked) return;                          // injected from the list (k_inject)
     const LevelDev &Pl = level_of(d, C.parent);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int ny = C.ny, nx = C.nx;
@@ -231,6 +222,32 @@ __global__ __launch_bounds__(256) void k_jnq(DomainDev d, int b)
     } else if (k < 2 * ny + 2 * nx) {
         const int i = k - 2 * ny - nx;
         CN[i + CP * ny] = PN[(I0 + i / 3) + PP * (J0 + fh)];
+    }
+}
+
+// Parent -> child on the boundary of masked children (Sec. IV-A, the flux
+// exchange): one thread per parent face between a covered and an uncovered
+// parent cell copies its new flux per unit width to the 3 child faces on it.
+template <typename F>
+__global__ __launch_bounds__(256) void k_inject(DomainDev d, int b)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d.ninject) return;
+    const int4 q = reinterpret_cast<const int4 *>(d.inject)[e];
+    const LevelDev &C = d.lv[q.x & 0xffff];
+    const LevelDev &Pl = d.lv[q.x >> 16];
+    if (q.y == 0) {
+        const F v = static_cast<const F *>(Pl.M[b ^ 1])[q.w];
+        F *cm = static_cast<F *>(C.M[b ^ 1]);
+        cm[q.z] = v;
+        cm[q.z + C.pitch] = v;
+        cm[q.z + 2 * C.pitch] = v;
+    } else {
+        const F v = static_cast<const F *>(Pl.N[b ^ 1])[q.w];
+        F *cn = static_cast<F *>(C.N[b ^ 1]);
+        cn[q.z] = v;
+        cn[q.z + 1] = v;
+        cn[q.z + 2] = v;
     }
 }
 
@@ -363,7 +380,8 @@ hipError_t launch_mass(const DomainDev &d, int b, hipStream_t s)
 hipError_t launch_jnz(const DomainDev &d, int b, hipStream_t s)
 {
     if (d.nlev < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_jnz, dim3((d.max_ring + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    if (d.nring == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jnz, dim3((d.nring + 255) / 256), dim3(256), 0, s, d, b);
     return hipGetLastError();
 }
 
@@ -377,6 +395,17 @@ hipError_t launch_jnq(const DomainDev &d, int b, hipStream_t s)
 {
     if (d.nlev < 2) return hipSuccess;
     hipLaunchKernelGGL(k_jnq, dim3((d.max_edge + 255) / 256, d.nlev - 1), dim3(256), 0, s, d, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject(const DomainDev &d, int b, hipStream_t s)
+{
+    if (d.ninject == 0) return hipSuccess;
+    const dim3 grid((d.ninject + 255) / 256);
+    if (d.bulk32)
+        hipLaunchKernelGGL(k_inject<float>, grid, dim3(256), 0, s, d, b);
+    else
+        hipLaunchKernelGGL(k_inject<double>, grid, dim3(256), 0, s, d, b);
     return hipGetLastError();
 }
 

@@ -34,7 +34,18 @@ struct LevelPlan {
     size_t eta_bytes;                       // one pitched FP64 cell array (eta)
     size_t cells_bytes, xf_bytes, yf_bytes; // one pitched array of h/maxima, M, N in the bulk precision
     int tiles_x, tiles_y, s_tiles_x, s_tiles_y;
+    // Masked level (touching blocks held as one level): inside[i + nx*j] = 1 for
+    // the cells of the level, cover[I + (nx/3)*J] = 1 for the parent cells it
+    // covers (their 3x3 cells inside).  Both empty for a rectangular level.
+    std::vector<uint8_t> inside, cover;
+    int64_t cells = 0;                      // cells inside the level
 };
+
+// Depth stored on the device for cells outside a masked level: ground far
+// above any water level, so every face touching such a cell is dry (Eq. (1)
+// then keeps its level exactly at -h: its neighbours' fluxes are far below
+// the rounding of that level).  The host reads such cells back as 0.
+constexpr double kOutsideDepth = -1e30;
 
 struct Plan {
     std::vector<LevelPlan> lv;
@@ -48,6 +59,8 @@ struct Plan {
                                   // whose edge faces lie in the tile's output rows and columns
     size_t dep_cap = 0;           // device entries reserved for dep (a tile whose list does not fit is pinned)
     std::vector<int32_t> ring;    // 2 per ring cell of every child: child level | parent level << 16, (J << 16) | I
+    std::vector<int32_t> inject;  // 4 per boundary face of every masked child (DomainDev::inject)
+    int64_t cells = 0;            // cells inside the levels
     size_t ring_bytes = 0;        // the parents' ring-mean arrays (one eta-sized array per level with children)
     size_t elem = sizeof(double); // element size of h, maxima, M, N
     size_t level_bytes = 0;       // the level arrays (state, bathymetry, maxima), first in memory
@@ -91,6 +104,7 @@ struct rti_domain {
     int32_t *dep_off_dev = nullptr, *dep_dev = nullptr;
     uint32_t *tcmask_dev = nullptr;
     int32_t *ring_dev = nullptr;         // the ring-cell list (Plan::ring)
+    int32_t *inject_dev = nullptr;       // the masked children's boundary faces (Plan::inject)
     char *ring_mem = nullptr;            // start of the parents' ring-mean arrays (ring_bytes)
     int cur = 0;                         // buffer holding the current state
     int64_t steps = 0;

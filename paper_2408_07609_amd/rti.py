@@ -34,7 +34,8 @@ _dptr = ctypes.POINTER(ctypes.c_double)
 
 class rti_level_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("parent", ctypes.c_int32),
-                ("off_i", ctypes.c_int32), ("off_j", ctypes.c_int32), ("h", _dptr)]
+                ("off_i", ctypes.c_int32), ("off_j", ctypes.c_int32), ("h", _dptr),
+                ("mask", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class rti_domain_desc(ctypes.Structure):
@@ -336,14 +337,18 @@ def rti_strerror(code: int) -> str:
 def make_desc(levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 0, 0), x0=0.0, y0=0.0,
               precision=RTI_FP64, flags=0):
     """Build an rti_domain_desc from level dicts (nx, ny, parent, off_i, off_j,
-    h as an (ny, nx) array).  Returns (desc, keepalive)."""
+    h as an (ny, nx) array, optionally mask as an (ny, nx) 0/1 array: the
+    cells inside a level of touching blocks).  Returns (desc, keepalive)."""
     hs = [np.ascontiguousarray(lv["h"], dtype=np.float64) for lv in levels]
+    masks = [None if lv.get("mask") is None else np.ascontiguousarray(lv["mask"], dtype=np.uint8) for lv in levels]
     arr = (rti_level_desc * len(levels))()
     for k, lv in enumerate(levels):
         arr[k].nx, arr[k].ny = int(lv["nx"]), int(lv["ny"])
         arr[k].parent = int(lv["parent"])
         arr[k].off_i, arr[k].off_j = int(lv.get("off_i", 0)), int(lv.get("off_j", 0))
         arr[k].h = hs[k].ctypes.data_as(_dptr)
+        if masks[k] is not None:
+            arr[k].mask = masks[k].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     d = rti_domain_desc()
     d.n_levels = len(levels)
     d.levels = ctypes.cast(arr, ctypes.POINTER(rti_level_desc))
@@ -352,7 +357,7 @@ def make_desc(levels, dx0, dt, g=9.81, manning_n=0.025, dry_eps=0.01, bc=(0, 0, 
     for q in range(4):
         d.bc[q] = int(bc[q])
     d.precision, d.flags = int(precision), int(flags)
-    return d, (arr, hs)
+    return d, (arr, hs, masks)
 
 
 class Domain:

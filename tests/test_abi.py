@@ -94,6 +94,37 @@ def test_validation_codes():
     assert "margin" in rti.rti_last_error()
 
 
+def test_validation_codes_masked_levels():
+    """Masks (touching blocks held as one level): the library accepts and
+    rejects the layouts the oracle's validation does, with the same codes."""
+    import oracle
+    import scenarios
+    sc = scenarios.small_union()
+    L = sc.levels
+    cases = [L]
+    child = dict(L[1], mask=L[1]["mask"].copy())
+    child["mask"][0, 0] = 1 - child["mask"][0, 0]
+    cases.append([L[0], child, L[2]])                                       # not constant over a 3x3 block
+    cases.append([L[0], dict(L[1], mask=np.zeros_like(L[1]["mask"]))])      # covers nothing
+    cases.append([dict(L[0], mask=np.ones((L[0]["ny"], L[0]["nx"]), dtype=np.uint8))] + L[1:])   # on the root
+    cases.append([L[0], L[1], dict(L[2], off_i=15)])                        # 3 cells of margin: fine
+    cases.append([L[0], L[1], dict(L[2], off_i=16)])                        # 2 cells from an outside cell
+    deep = np.where(L[1]["mask"] != 0, L[1]["h"], 5000.0)
+    cases.append([L[0], dict(L[1], h=deep), L[2]])                          # outside cells do not count in Eq. (4)
+    nan = np.where(L[1]["mask"] != 0, L[1]["h"], np.nan)
+    cases.append([L[0], dict(L[1], h=nan), L[2]])                           # nor in the finiteness check
+    want = [oracle.OK, oracle.ENEST, oracle.ENEST, oracle.ENEST, oracle.OK, oracle.ENEST, oracle.OK]
+    for q, levels in enumerate(cases):
+        got = code_of(levels, dx0=sc.dx0, dt=sc.dt)
+        if q < len(want):
+            assert oracle.validate(levels, sc.dx0, sc.dt) == want[q], f"case {q}: oracle"
+            assert got == want[q], f"case {q}: library code {got}, want {want[q]} ({rti.rti_last_error()})"
+        else:
+            assert got == rti.RTI_OK, f"case {q}: {rti.rti_last_error()}"
+    bad = dict(L[1], mask=np.where(L[1]["mask"] != 0, 2, 0).astype(np.uint8))
+    assert code_of([L[0], bad, L[2]], dx0=sc.dx0, dt=sc.dt) == rti.RTI_EINVAL
+
+
 def test_null_arguments():
     assert rti.LIB.rti_domain_footprint(None, None) == rti.RTI_EINVAL
     assert rti.LIB.rti_step(None, 1) == rti.RTI_EINVAL

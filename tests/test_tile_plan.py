@@ -56,7 +56,8 @@ class Grid:
             ny, nx = L["h"].shape
             f = 1 if k == 0 else 0
             tx, ty = (nx + f + TW - 1) // TW, (ny + f + th - 1) // th
-            self.lv.append(dict(nx=nx, ny=ny, tx=tx, ty=ty, parent=L["parent"], oi=L["off_i"], oj=L["off_j"]))
+            cov = None if L.get("mask") is None else np.asarray(L["mask"]).reshape(ny, nx)[::3, ::3] != 0
+            self.lv.append(dict(nx=nx, ny=ny, tx=tx, ty=ty, parent=L["parent"], oi=L["off_i"], oj=L["off_j"], cov=cov))
             self.base.append(n)
             n += tx * ty
         self.ntiles = n
@@ -70,6 +71,24 @@ class Grid:
 
     def children(self, l):
         return [k for k, L in enumerate(self.lv) if L["parent"] == l]
+
+    def covers(self, k, I, J):
+        """Does level k cover parent cell (I, J) of its footprint?"""
+        C = self.lv[k]
+        if not (0 <= I < C["nx"] // 3 and 0 <= J < C["ny"] // 3):
+            return False
+        return C["cov"] is None or bool(C["cov"][J, I])
+
+    def ring(self, k, I, J):
+        """Ring cell of child k (Sec. IV-C): covered, with an uncovered 8-neighbour."""
+        return self.covers(k, I, J) and not all(self.covers(k, I + a, J + b) for a in (-1, 0, 1) for b in (-1, 0, 1))
+
+    def xface_injected(self, k, fi, jj):
+        """Is child x-face (fi, jj) of level k injected by its parent?"""
+        return fi % 3 == 0 and self.covers(k, fi // 3 - 1, jj // 3) != self.covers(k, fi // 3, jj // 3)
+
+    def yface_injected(self, k, ii, fj):
+        return fj % 3 == 0 and self.covers(k, ii // 3, fj // 3 - 1) != self.covers(k, ii // 3, fj // 3)
 
 
 def required(G, l, tx, ty):
@@ -100,33 +119,32 @@ def required(G, l, tx, ty):
                 continue
             for t in rows:
                 J = t - C["oj"]
-                if not 0 <= J < fh or not (I in (0, fw - 1) or J in (0, fh - 1)):
+                if not 0 <= J < fh or not G.ring(k, I, J):
                     continue
                 ring = True
                 for jj in range(3 * J, 3 * J + 3):
                     for ii in range(3 * I, 3 * I + 3):
                         other.add(G.tile(k, ii, jj))                 # eta, h of the child cell
                         for fi in (ii, ii + 1):                      # its x-faces
-                            if fi in (0, C["nx"]):
+                            if G.xface_injected(k, fi, jj):
                                 own.add(G.tile(l, C["oi"] + fi // 3, C["oj"] + jj // 3))   # injected by this level
                             else:
                                 other.add(G.tile(k, fi, jj))
                         for fj in (jj, jj + 1):                      # its y-faces
-                            if fj in (0, C["ny"]):
+                            if G.yface_injected(k, ii, fj):
                                 own.add(G.tile(l, C["oi"] + ii // 3, C["oj"] + fj // 3))
                             else:
                                 other.add(G.tile(k, ii, fj))
     if l > 0:
         p = L["parent"]
-        fw, fh = nx // 3, ny // 3
-        for i in (0, nx):
-            if x0 - 2 <= i <= x0 + 62:
-                for j in range(max(y0 - 2, 0), min(t1, ny - 1) + 1):
+        for i in range(max(x0 - 2, 0), min(x0 + 62, nx) + 1):
+            for j in range(max(y0 - 2, 0), min(t1, ny - 1) + 1):
+                if G.xface_injected(l, i, j):
                     inj = True
                     other.add(G.tile(p, L["oi"] + i // 3, L["oj"] + j // 3))
-        for j in (0, ny):
-            if y0 - 2 <= j <= t1 + 1:
-                for i in range(max(x0 - 2, 0), min(x0 + 61, nx - 1) + 1):
+        for j in range(max(y0 - 2, 0), min(t1 + 1, ny) + 1):
+            for i in range(max(x0 - 2, 0), min(x0 + 61, nx - 1) + 1):
+                if G.yface_injected(l, i, j):
                     inj = True
                     other.add(G.tile(p, L["oi"] + i // 3, L["oj"] + j // 3))
     return own, other, ring, inj
@@ -250,6 +268,9 @@ def check_plan(sc, th, name):
                     # the child mask holds every child whose edge faces lie in the tile's output
                     for q, k in enumerate(G.children(l)[:32]):
                         C = G.lv[k]
+                        if C["cov"] is not None:
+                            assert not plan.cmask[g] >> q & 1, f"tile {g}: masked child {k} in the mask"
+                            continue              # its boundary is injected after the launch, from a list
                         fw, fh = C["nx"] // 3, C["ny"] // 3
                         ox = range(tx * TW, tx * TW + TW)
                         oy = range(ty * th, ty * th + th)
@@ -260,6 +281,28 @@ def check_plan(sc, th, name):
                 missing = other - set(lst.tolist())
                 assert not missing, f"{name} th={th} tile {g} (level {l}, {tx},{ty}): writers {sorted(missing)} not coupled"
     assert n_dep_tiles > 0
+
+
+def masked_cases():
+    import pins
+    merged, _, _ = pins.merge_siblings(scenarios.small_blocks().levels, 1, 2)
+    u = scenarios.Scenario("u-shape", [dict(nx=45, ny=33, parent=-1, off_i=0, off_j=0, h=np.ones((33, 45)))],
+                           dx0=810.0, dt=0.2, steps=0)
+    u.levels.append(scenarios.union_level(0, [(12, 9, 21, 4), (12, 13, 6, 8), (27, 13, 6, 8)]))
+    u.levels[1]["h"] = np.ones((u.levels[1]["ny"], u.levels[1]["nx"]))
+    return {
+        "small_union": scenarios.small_union(),
+        "merged_blocks": scenarios.Scenario("merged", merged, dx0=810.0, dt=0.2, steps=0),
+        "u_shape": u,
+    }
+
+
+@pytest.mark.parametrize("name", ["small_union", "merged_blocks", "u_shape"])
+@pytest.mark.parametrize("th", [4, 5, 7, 12])
+def test_coupled_tiles_masked_levels(name, th):
+    """Levels of touching blocks (masks): ring means at inner corners, and
+    boundary faces inside the rectangle injected from the parent."""
+    check_plan(masked_cases()[name], th, name)
 
 
 def test_root_only_has_no_coupled_tiles():
