@@ -16,7 +16,8 @@ steps' set-up always happen before the timed window.  In the dense case the
 whole 6-hour run is measured too, in the same process, and reported as
 "full_run".  Prints one JSON line on stdout; progress on stderr.
 --config c1/c2: the smaller configurations; c3b: C3 split into the 84 blocks
-of the paper's Table 1; c4: the batched ensemble (48 uneven scenarios,
+of the paper's Table 1, each in its own parent block; c3t: the same block
+counts as touching rectangles, one masked level per resolution; c4: the batched ensemble (48 uneven scenarios,
 FP32-bulk, one batch); c5: forecast serving (Poisson arrivals, continuous
 batching, p50/p99 time to forecast).
 """
@@ -141,12 +142,13 @@ def _oracle_rate(sc, seconds):
     return sc.cells * done / el, done, el, oracle.threads()
 
 
-SCENARIOS = ("c1", "c2", "c3", "c3b")
+SCENARIOS = ("c1", "c2", "c3", "c3b", "c3t")
 
 
 def scenario(name):
     import scenarios
-    return {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3, "c3b": scenarios.c3_blocks}[name]()
+    return {"c1": scenarios.c1, "c2": scenarios.c2, "c3": scenarios.c3, "c3b": scenarios.c3_blocks,
+            "c3t": scenarios.c3_touching}[name]()
 
 
 def cpu_baseline(sc, seconds, config=None):
@@ -617,7 +619,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole configuration)")
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c3b", "c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c3b", "c3t", "c4", "c5"])
     ap.add_argument("--flags", type=int, default=0, help="RTI_FLAG_* bits for the domain")
     ap.add_argument("--tile-rows", type=int, default=0, help="tile height of the fused kernel (0: the library's default)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-bulk"])

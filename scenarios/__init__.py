@@ -367,6 +367,65 @@ def c3_blocks(seed: int = 3) -> Scenario:
     return sc
 
 
+def _touching_chain(sc: Scenario, coast, specs):
+    """Append one masked level per resolution, each the child of the last.
+    specs: (rows, cols, w, h) per resolution: a grid of rows x cols touching
+    blocks of w x h parent cells (3w x 3h cells of their own); each row of
+    blocks is centred on the coast at its mid-height, the rows stacked along
+    y without gaps, and kept 3 parent cells inside the parent's own cells."""
+    for (nr, ncol, w, h) in specs:
+        p = len(sc.levels) - 1
+        P = sc.levels[p]
+        inside = np.ones((P["ny"], P["nx"]), dtype=bool) if P.get("mask") is None else P["mask"] != 0
+        if P.get("mask") is None:                       # the rectangle rule: 3 cells from the parent's edge
+            inside[:3, :] = inside[-3:, :] = False
+            inside[:, :3] = inside[:, -3:] = False
+        pdx = sc.level_dx(p)
+        pox, poy = sc.level_origin(p)
+        rows_in = np.flatnonzero(inside.any(axis=1))
+        span = rows_in[-1] - rows_in[0] + 1
+        assert nr * h <= span - 6, f"{nr} rows of {h} parent cells do not fit in {span} rows"
+        y0 = int(rows_in[0] + (span - nr * h) // 2)
+        rects = []
+        for r in range(nr):
+            y = y0 + r * h
+            band = inside[y - 3:y + h + 3]
+            lo = max(int(np.flatnonzero(row)[0]) for row in band) + 3
+            hi = min(int(np.flatnonzero(row)[-1]) + 1 for row in band) - 3 - ncol * w
+            assert lo <= hi, f"a row of {ncol} blocks of {w} cells does not fit at rows {y}..{y + h}"
+            cx = float(coast.xc(np.array([poy + (y + h / 2) * pdx]))[0])
+            x = int(round((cx - pox) / pdx - ncol * w / 2))
+            x = min(max(x, lo), hi)
+            rects += [(x + c * w, y, w, h) for c in range(ncol)]
+        sc.levels.append(union_level(p, rects))
+
+
+def c3_touching(seed: int = 3) -> Scenario:
+    """C3 with the paper's block counts (Table 1: 3, 9, 11 and 60 blocks at
+    270, 90, 30 and 10 m) as touching rectangles: every resolution is one
+    band of blocks that share edges, stepping along the seeded coast of C3
+    (one masked level per resolution).  The root and the coast are C3's; the
+    levels hold 46,983,789 cells in all (the paper: 47,211,444)."""
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 1266, 1590
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.72 * Lx, Ly, wiggle=5e3,
+                   knots=[(0.0, 0.0), (45e3, 100.0), (90e3, 1000.0), (250e3, 5000.0), (1e9, 5000.0)],
+                   zmax=30.0, slope=1.0 / 1000.0, Lx=Lx, nbumps=6, scale=1)
+    sc = Scenario("c3-touching", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=108000)
+    _touching_chain(sc, coast, [(3, 1, 67, 77),        # 270 m: 3 blocks of 201 x 231
+                                (9, 1, 140, 76),       # 90 m: 9 blocks of 420 x 228
+                                (11, 1, 294, 186),     # 30 m: 11 blocks of 882 x 558
+                                (12, 5, 140, 510)])    # 10 m: 60 blocks of 420 x 1530
+    _fill_depths(sc, coast)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    sc.source = Source(cx - 150e3, cy, 50e3, 25e3, 0.5 * math.pi, 3.0, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
 def small_blocks(seed: int = 21) -> Scenario:
     """A small multi-block nest for step-level tests: a 90x96 root at 810 m,
     2 blocks at 270 m, 3 at 90 m (two in one parent) and 2 at 30 m, with a

@@ -60,6 +60,15 @@ def test_c3_blocks_full_size_steps():
         assert max(w) <= 1e-9, f"block {k}: {w}"
 
 
+@pytest.mark.timeout(1200)
+def test_c3_touching_full_size_steps():
+    """The paper's 3/9/11/60 blocks at 270/90/30/10 m as touching
+    rectangles, one masked level per resolution (46,983,789 cells)."""
+    sc = scenarios.c3_touching()
+    for k, w in run_random(sc, 2, seed=305).items():
+        assert max(w) <= 1e-9, f"level {k}: {w}"
+
+
 @pytest.mark.timeout(900)
 def test_c2_full_size_steps():
     sc = scenarios.c2()
@@ -114,5 +123,27 @@ def test_c3_blocks_tile_skipping_is_exact():
     for k in range(len(sc.levels)):
         for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
             assert np.array_equal(x, y), f"block {k}"
+    a.close()
+    b.close()
+
+
+@pytest.mark.timeout(900)
+def test_c3_touching_tile_skipping_is_exact():
+    """The touching-block layout from its source for 1500 steps, skipping
+    stationary tiles (the tiles wholly outside the staircase bands among
+    them) against computing every tile: bitwise equal."""
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE
+    sc = scenarios.c3_touching()
+    a, b = gpu_domain(sc), gpu_domain(sc, flags=RTI_FLAG_NO_ACTIVE)
+    for d in (a, b):
+        d.set_source(*sc.source.astuple())
+        d.step(1500)
+        d.sync()
+    all_, computed = a.cell_updates()
+    print(f"computed {computed} of {all_} cell updates ({computed / all_:.3f})")
+    assert computed < 0.9 * all_
+    for k in range(len(sc.levels)):
+        for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
+            assert np.array_equal(x, y), f"level {k}"
     a.close()
     b.close()
