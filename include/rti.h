@@ -118,7 +118,7 @@ typedef struct {
     double dt;                       /* time step [s], all levels */
     double g;                        /* gravity [m/s^2] (9.81) */
     double manning_n;                /* Manning roughness [s m^-1/3] (0.025) */
-    double dry_eps;                  /* dry threshold on total depth [m] (0.01) */
+    double dry_eps;                  /* dry threshold on total depth [m] (0.01; at least 1e-12) */
     int32_t bc[4];                   /* root sides W, E, S, N: RTI_BC_OPEN or RTI_BC_WALL */
     int32_t precision;               /* RTI_FP64 or RTI_FP32_BULK (not with RTI_FLAG_PHASED) */
     uint32_t flags;                  /* RTI_FLAG_* */
@@ -325,8 +325,9 @@ void rti_batch_destroy(rti_batch *batch);
  * FP64 results are bitwise reproducible only because each of them is
  * correctly rounded).  op: RTI_PROBE_CBRT, the cube root of the Manning term
  * (Eqs. 2-3: D^(-7/3) = (1/D)^2 cbrt(1/D)), defined for positive normal x;
- * RTI_PROBE_RECIP, the reciprocal 1/x of a face depth; RTI_PROBE_SQRT, the
- * square root.  x and y are device arrays of n doubles (y may alias x); the
+ * RTI_PROBE_RECIP, the reciprocal 1/x of a face depth, defined for x in
+ * [2^-767, 2^1022) (every face depth of a step lies there); RTI_PROBE_SQRT,
+ * the square root.  x and y are device arrays of n doubles (y may alias x); the
  * kernel is enqueued on hip_stream (borrowed, NULL = default stream) and the
  * call returns without waiting.  RTI_EINVAL for an unknown op, n < 0 or a NULL
  * array with n > 0. */

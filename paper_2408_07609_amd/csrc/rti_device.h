@@ -142,34 +142,45 @@ __device__ __forceinline__ double cbrt_rn_reduced(double x)
 // bounds above do not depend on the scale), falling back to the reduced
 // form outside that range and whenever the root lies too near a midpoint
 // for the fast decision.  Correctly rounded for every positive normal x.
+// Outside [2^-120, 2^120] the unreduced steps may produce anything (an
+// infinite or zero estimate); they are computed regardless and their result
+// discarded, which costs less than selecting a safe operand first.
 __device__ __forceinline__ double cbrt_rn(double x)
 {
-    double r;
-    bool slow = !(x >= 0x1p-120 && x <= 0x1p120);
-    {
-        const float xf = (float)(slow ? 1.0 : x);
-        double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf(xf));
-        const double xs = slow ? 1.0 : x;
-        const double e = fma(-xs, (z * z) * z, 1.0);
-        z = fma(z * e, fma(e, 2.0 / 9.0, 1.0 / 3.0), z);
-        const double y = (xs * z) * z;
-        const double p = y * y, pl = fma(y, y, -p);
-        const double t = p * y, tl = fma(p, y, -t);
-        const double res = ((xs - t) - tl) - pl * y;
-        const double d = res * ((z * z) * (1.0 / 3.0));
-        const double s = y + d;
-        const double err = d - (s - y);
-        const long long bits = __double_as_longlong(s);
-        const double nb = __longlong_as_double(err > 0.0 ? bits + 1 : bits - 1);
-        slow = slow || (fabs(err) > fabs(0.5 * (nb - s)) * (1.0 - 0x1p-20));
-        r = s;
-    }
+    double z = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf((float)x));
+    const double e = fma(-x, (z * z) * z, 1.0);
+    z = fma(z * e, fma(e, 2.0 / 9.0, 1.0 / 3.0), z);
+    const double y = (x * z) * z;
+    const double p = y * y, pl = fma(y, y, -p);
+    const double t = p * y, tl = fma(p, y, -t);
+    const double res = ((x - t) - tl) - pl * y;
+    const double d = res * ((z * z) * (1.0 / 3.0));
+    const double s = y + d;
+    const double err = d - (s - y);
+    const long long bits = __double_as_longlong(s);
+    const double nb = __longlong_as_double(err > 0.0 ? bits + 1 : bits - 1);
+    const bool slow = !(x >= 0x1p-120 && x <= 0x1p120) || (fabs(err) > fabs(0.5 * (nb - s)) * (1.0 - 0x1p-20));
+    double r = s;
     if (slow) r = cbrt_rn_reduced(x);
     return r;
 }
 
-// Reciprocal of a face depth: IEEE division in FP64.
-__device__ __forceinline__ double inv_depth(double D) { return 1.0 / D; }
+// Reciprocal of a face depth, correctly rounded (the IEEE quotient 1/D) for
+// D in [2^-767, 2^1022): the steps of the correctly rounded division --
+// hardware reciprocal estimate, two Newton steps, the quotient, its exact
+// residual and the final correction -- without its operand scaling and
+// special-value fix-up, which are identities on that range (no operand or
+// result near the limits of the format).  A face depth lies there: an active
+// face's exceeds the dry threshold (at least 1e-12, checked at create), an
+// inactive face's is 1, and depths are far below 2^1022 m in any state the
+// watchdog has not flagged.
+__device__ __forceinline__ double inv_depth(double D)
+{
+    double r = __builtin_amdgcn_rcp(D);
+    r = fma(r, fma(-D, r, 1.0), r);
+    r = fma(r, fma(-D, r, 1.0), r);
+    return fma(fma(-D, r, 1.0), r, r);
+}
 __device__ __forceinline__ float inv_depth(float D) { return recip(D); }
 
 // Momentum flux quantity a*b/D given 1/D.

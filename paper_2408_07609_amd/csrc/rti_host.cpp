@@ -266,9 +266,9 @@ int plan_domain(const rti_domain_desc *d, Plan &plan)
     if (d->n_levels < 1 || d->n_levels > RTI_MAX_LEVELS)
         return fail(RTI_EINVAL, "n_levels %d outside [1, %d]", d->n_levels, RTI_MAX_LEVELS);
     if (!d->levels) return fail(RTI_EINVAL, "levels is NULL");
-    if (!(d->dt > 0.0) || !(d->dx0 > 0.0) || !(d->g > 0.0) || !(d->manning_n >= 0.0) || !(d->dry_eps > 0.0)
+    if (!(d->dt > 0.0) || !(d->dx0 > 0.0) || !(d->g > 0.0) || !(d->manning_n >= 0.0) || !(d->dry_eps >= 1e-12)
         || !std::isfinite(d->dt) || !std::isfinite(d->dx0) || !std::isfinite(d->x0) || !std::isfinite(d->y0))
-        return fail(RTI_EINVAL, "dt, dx0, g, dry_eps must be positive and finite, manning_n >= 0");
+        return fail(RTI_EINVAL, "dt, dx0, g must be positive and finite, dry_eps >= 1e-12, manning_n >= 0");
     for (int s = 0; s < 4; ++s)
         if (d->bc[s] != RTI_BC_OPEN && d->bc[s] != RTI_BC_WALL) return fail(RTI_EINVAL, "bc[%d] = %d", s, d->bc[s]);
     if (d->precision != RTI_FP64 && d->precision != RTI_FP32_BULK)

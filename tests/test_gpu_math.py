@@ -50,7 +50,14 @@ def test_cbrt_is_correctly_rounded():
 def test_reciprocal_and_sqrt_are_ieee():
     from paper_2408_07609_amd import rti
     x = inputs(seed=14)
-    assert np.array_equal(probe(rti.RTI_PROBE_RECIP, x), 1.0 / x)
+    d = x[(x >= 2.0 ** -767) & (x < 2.0 ** 1022)]                 # the face-depth reciprocal's domain
+    assert d.size > 0.9 * x.size
+    assert np.array_equal(probe(rti.RTI_PROBE_RECIP, d), 1.0 / d)
+    rng = np.random.default_rng(16)                                # near the ends of the domain and at powers of 2
+    edge = np.concatenate([np.exp2(rng.uniform(-767.0, -700.0, 100_000)), np.exp2(rng.uniform(950.0, 1021.99, 100_000)),
+                           np.exp2(np.arange(-767.0, 1022.0)), np.nextafter(np.exp2(np.arange(-766.0, 1022.0)), 0.0),
+                           np.array([1e-12, 0.01, 1.0, 3.0, 6000.0])])
+    assert np.array_equal(probe(rti.RTI_PROBE_RECIP, edge), 1.0 / edge)
     assert np.array_equal(probe(rti.RTI_PROBE_SQRT, x), np.sqrt(x))
     sq = np.random.default_rng(15).uniform(0.0, 2.0e5, size=100_000)     # g h and M^2 + N^2 ranges
     assert np.array_equal(probe(rti.RTI_PROBE_SQRT, sq), np.sqrt(sq))
