@@ -1,8 +1,9 @@
 // A driver of the library's host runtime for the AddressSanitizer / UBSan
 // build (tests/test_sanitizers.py): descriptor validation (valid layouts,
-// CFL and nesting violations, bad arguments), the footprint, the fused
-// kernel's tile plan at several tile heights, error strings, and the
-// diagnostics' argument checks -- every path that runs without a GPU.
+// CFL and nesting violations, bad arguments, masked levels of touching
+// blocks), the footprint, the fused kernel's tile plan at several tile
+// heights, error strings, and the diagnostics' argument checks -- every path
+// that runs without a GPU.
 // Exit 0 when every call returns the expected code.
 #include <cstdio>
 #include <cstdlib>
@@ -56,6 +57,35 @@ int main()
             for (int k = off[g]; k < off[g + 1]; ++k)
                 if (dep[k] < 0 || dep[k] >= nt) ++failures;
     }
+    // the middle level as an L of two touching blocks (parent cells (6.., 5..) left out), its child
+    // inside the L with 3 cells of margin, then a mask that is not constant over a 3x3 block
+    std::vector<uint8_t> m1(36 * 27);
+    for (int j = 0; j < 27; ++j)
+        for (int i = 0; i < 36; ++i) m1[(size_t)j * 36 + i] = !(i >= 18 && j >= 15);
+    lv[1].mask = m1.data();
+    lv[2].nx = 9;
+    lv[2].ny = 9;
+    expect(rti_domain_footprint(&d, &bytes), RTI_OK, "footprint of a masked level");
+    for (int th : {4, 7, 12}) {
+        int32_t nt = 0, nd = 0;
+        expect(rti_plan_tiles_for_test(&d, th, &nt, &nd, nullptr, nullptr, nullptr, nullptr, nullptr), RTI_OK,
+               "masked plan sizes");
+        std::vector<uint8_t> tinfo(nt), tlev(nt);
+        std::vector<int32_t> off(nt + 1), dep(nd > 0 ? nd : 1);
+        std::vector<uint32_t> mask(nt);
+        expect(rti_plan_tiles_for_test(&d, th, &nt, &nd, tinfo.data(), tlev.data(), off.data(), dep.data(), mask.data()),
+               RTI_OK, "masked plan tables");
+    }
+    lv[2].off_i = 14;                                    // the child's columns reach parent cell 16: 2 from the outside
+    lv[2].off_j = 10;
+    expect(rti_domain_footprint(&d, &bytes), RTI_ENEST, "child within 3 cells of a masked parent's outside");
+    lv[2].off_i = 3;
+    lv[2].off_j = 3;
+    m1[5] = 0;                                           // one cell of a 3x3 block
+    expect(rti_domain_footprint(&d, &bytes), RTI_ENEST, "mask not constant over a 3x3 block");
+    lv[1].mask = nullptr;
+    lv[2].nx = 27;
+    lv[2].ny = 27;
     rti_domain_desc bad = d;
     lv[1].nx = 35;                                       // not a multiple of 3
     expect(rti_domain_footprint(&bad, &bytes), RTI_ENEST, "child nx not a multiple of 3");

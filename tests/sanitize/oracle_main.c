@@ -1,8 +1,9 @@
 /* A small driver of the CPU oracle for the AddressSanitizer / UBSan build
  * (tests/test_sanitizers.py): a 2-level nest over a sloping coast with a
- * child straddling the shoreline, the elliptic source, 300 steps, and the
- * correctly rounded cube root over a range of depths and near binade edges.
- * Exit 0 when every value stays finite. */
+ * child straddling the shoreline (an L of two touching blocks: a mask leaves
+ * out the north-east corner of its rectangle), the elliptic source, 300
+ * steps, and the correctly rounded cube root over a range of depths and near
+ * binade edges.  Exit 0 when every value stays finite. */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -12,6 +13,7 @@ typedef struct {
     int32_t nx, ny, parent, off_i, off_j;
     double dx, ox, oy;
     double *h, *eta, *M, *N, *zmax, *M2, *N2, *clip;
+    const uint8_t *mask;
 } ora_level;
 typedef struct {
     int32_t nlev;
@@ -65,6 +67,10 @@ int main(void)
     lv[1].dx = 270.0;
     lv[1].ox = 22 * 810.0;
     lv[1].oy = 12 * 810.0;
+    uint8_t *mask = malloc((size_t)36 * 27);
+    for (int j = 0; j < 27; j++)
+        for (int i = 0; i < 36; i++) mask[(size_t)j * 36 + i] = !(i >= 18 && j >= 15);   /* parent cells (6.., 5..) out */
+    lv[1].mask = mask;
     for (int l = 0; l < 2; l++) {
         ora_level *L = &lv[l];
         for (int j = 0; j < L->ny; j++)
@@ -89,6 +95,7 @@ int main(void)
     s += ora_cbrt_rn(nextafter(1.0, 0.0)) + ora_cbrt_rn(8.0) + ora_cbrt_rn(nextafter(2.0, 4.0)) + ora_cbrt_rn(0x1p-1000);
     if (!isfinite(s)) return 1;
     for (int l = 0; l < 2; l++) free_level(&lv[l]);
+    free(mask);
     printf("oracle ok: %lld steps\n", (long long)d.steps);
     return 0;
 }
