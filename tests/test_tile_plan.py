@@ -297,6 +297,47 @@ def masked_cases():
     }
 
 
+def random_union(seed):
+    """A random level of 2-4 touching blocks (a staircase of rectangles, each
+    row of blocks shifted in x from the one below, still sharing an edge with
+    it) in a random root, sometimes with a child inside one block; depths do
+    not matter to the plan."""
+    rng = np.random.default_rng(seed)
+    nx0, ny0 = int(rng.integers(80, 221)), int(rng.integers(60, 161))
+    root = dict(nx=nx0, ny=ny0, parent=-1, off_i=0, off_j=0, h=np.ones((ny0, nx0)))
+    rects, y, x = [], 3, int(rng.integers(3, nx0 // 3))
+    for _ in range(int(rng.integers(2, 5))):
+        w, hgt = int(rng.integers(8, 31)), int(rng.integers(4, 16))
+        if y + hgt > ny0 - 3 or x + w > nx0 - 3:
+            break
+        rects.append((x, y, w, hgt))
+        y += hgt
+        x = max(3, min(nx0 - 3 - w, x + int(rng.integers(-w + 1, w))))
+    if len(rects) < 2:
+        rects = [(3, 3, 8, 4), (5, 7, 8, 4)]
+    lv = scenarios.union_level(0, rects)
+    lv["h"] = np.ones((lv["ny"], lv["nx"]))
+    levels = [root, lv]
+    big = max(rects, key=lambda r: r[2] * r[3])
+    if big[2] >= 9 and big[3] >= 9 and rng.uniform() < 0.7:
+        ci, cj = 3 * (big[0] - lv["off_i"]) + 3, 3 * (big[1] - lv["off_j"]) + 3
+        levels.append(dict(nx=9 * ((big[2] - 2) // 3), ny=9 * ((big[3] - 2) // 3), parent=1, off_i=ci, off_j=cj,
+                           h=None))
+        levels[-1]["h"] = np.ones((levels[-1]["ny"], levels[-1]["nx"]))
+    return scenarios.Scenario(f"random-union-{seed}", levels, dx0=810.0, dt=0.2, steps=0)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_coupled_tiles_random_masked_levels(seed):
+    import oracle
+    sc = random_union(seed)
+    if oracle.validate(sc.levels, sc.dx0, sc.dt) != oracle.OK:      # a child too near the outside: drop it
+        sc.levels = sc.levels[:2]
+    assert oracle.validate(sc.levels, sc.dx0, sc.dt) == oracle.OK
+    for th in (4, 5, 9):
+        check_plan(sc, th, sc.name)
+
+
 @pytest.mark.parametrize("name", ["small_union", "merged_blocks", "u_shape"])
 @pytest.mark.parametrize("th", [4, 5, 7, 12])
 def test_coupled_tiles_masked_levels(name, th):
