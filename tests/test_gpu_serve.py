@@ -26,10 +26,10 @@ def test_served_forecasts_match_alone(precision):
     from paper_2408_07609_amd.serve import ForecastServer, Request, footprint
     sites = [scenarios.small_nested(seed=7, nlev=3), scenarios.small_nested(seed=11, nlev=2, base=(90, 72),
                                                                             child=(45, 54)),
-             scenarios.c2(scale=10)]
+             scenarios.c2(scale=10), scenarios.small_union()]
     reqs = []
     for rid, (k, steps, arrival) in enumerate([(0, 131, 0.0), (2, 97, 0.0), (1, 260, 0.0), (2, 45, 0.0),
-                                              (0, 77, 0.3), (1, 20, 0.35)]):
+                                              (0, 77, 0.3), (1, 20, 0.35), (3, 150, 0.1)]):
         s = sites[k].source
         src = (s.xc, s.yc, s.a, s.b, s.theta, 0.5 + 0.7 * rid, s.shape)
         reqs.append(Request(rid, sites[k], src, steps, arrival))
