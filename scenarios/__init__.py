@@ -400,6 +400,28 @@ def _touching_chain(sc: Scenario, coast, specs):
         sc.levels.append(union_level(p, rects))
 
 
+def small_touching(seed: int = 29) -> Scenario:
+    """A small chain of levels of touching blocks over a seeded coast: a
+    90x72 root at 810 m; at 270 m two blocks of 12x8 root cells, one above
+    the other; at 90 m a 3 x 2 grid of blocks of 9x7 cells at 270 m (each a
+    masked level whose rows of blocks step along the coast)."""
+    rng = np.random.default_rng(seed)
+    dx0 = 810.0
+    nx0, ny0 = 90, 72
+    Lx, Ly = nx0 * dx0, ny0 * dx0
+    coast = _Coast(rng, 0.6 * Lx, Ly, wiggle=0.06 * Ly,
+                   knots=[(0.0, 0.0), (0.1 * Lx, 20.0), (0.4 * Lx, 200.0), (1e12, 200.0)],
+                   zmax=5.0, slope=5.0 / (0.05 * Lx), Lx=Lx, nbumps=0, scale=1)
+    sc = Scenario("small-touching", [_level(nx0, ny0)], dx0=dx0, dt=0.2, steps=0)
+    _touching_chain(sc, coast, [(2, 1, 12, 8), (3, 2, 9, 7)])
+    _fill_depths(sc, coast)
+    cy = Ly / 2
+    cx = float(coast.xc(np.array([cy]))[0])
+    sc.source = Source(cx - 0.03 * Lx, cy, 0.08 * Lx, 0.3 * Ly, 0.0, 1.5, COS2_ELLIPSE)
+    sc.check_cfl()
+    return sc
+
+
 def c3_touching(seed: int = 3) -> Scenario:
     """C3 with the paper's block counts (Table 1: 3, 9, 11 and 60 blocks at
     270, 90, 30 and 10 m) as touching rectangles: every resolution is one

@@ -85,6 +85,20 @@ def test_union_source_run():
     assert np.all(d.get_state(1)[0][out] == 0.0) and np.all(d.max_inundation(1)[out] == 0.0)
 
 
+def test_touching_chain_source_run():
+    """Levels of touching blocks inside levels of touching blocks (a 3 x 2
+    grid of 90 m blocks in two stepped 270 m blocks): 600 steps bitwise the
+    oracle; every level floods."""
+    sc = scenarios.small_touching()
+    d, o = from_source(sc)
+    d.step(600)
+    o.step(600)
+    compare(d, o, len(sc.levels), "touching chain, 600 steps")
+    for k in (1, 2):
+        land = (sc.levels[k]["h"] <= 0) & (sc.levels[k]["mask"] != 0)
+        assert (o.max_inundation(k)[land] > 0.05).sum() > 10, f"level {k} does not flood"
+
+
 def test_merged_blocks_match_oracle():
     """Two 270 m blocks held as one masked level (and their children
     re-parented to it): bitwise the oracle after 300 steps."""
@@ -105,11 +119,12 @@ def test_union_lake_at_rest():
             assert np.array_equal(x, y), f"level {k} moved at rest"
 
 
-def test_union_skipping_and_phased_are_exact():
+@pytest.mark.parametrize("name", ["small_union", "small_touching"])
+def test_union_skipping_and_phased_are_exact(name):
     """The fused kernel with stationary tiles skipped, without skipping, and
     the per-phase kernels give bitwise the same run."""
     from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED
-    sc = scenarios.small_union()
+    sc = getattr(scenarios, name)()
     runs = []
     for flags in (0, RTI_FLAG_NO_ACTIVE, RTI_FLAG_PHASED):
         d = gpu(sc, flags=flags)
