@@ -410,12 +410,16 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
             F Mnew = (xp.act != 0) ? Mint : F(0);        // xp.act implies an interior face
             F Nnew = (yp.act != 0) ? Nint : F(0);
             if (root) {
-                const double mbv = (c == 0) ? (d.bc[0] ? 0.0 : radiate(d.g, eps, p.H, p.e1, -1.0))
-                                            : (d.bc[1] ? 0.0 : radiate(d.g, eps, p.HL, p.e1L, 1.0));
-                const double nbv = (rr == 0) ? (d.bc[2] ? 0.0 : radiate(d.g, eps, p.H, p.e1, -1.0))
-                                             : (d.bc[3] ? 0.0 : radiate(d.g, eps, pp.H, pp.e1, 1.0));
-                if (xf_here && !col_xint) Mnew = (F)mbv;
-                if (col_cell && !(rr >= 1 && rr <= ny - 1)) Nnew = (F)nbv;
+                // One radiation value per face kind: the west side's at column 0, the east side's at
+                // column nx (operands selected first, then one evaluation); the south side's at face
+                // row 0, the north side's at row ny.  A wall gives 0.
+                const bool west = (c == 0), south = (rr == 0);
+                const bool xopen = west ? (d.bc[0] == RTI_BC_OPEN_DEV) : (d.bc[1] == RTI_BC_OPEN_DEV);
+                const bool yopen = south ? (d.bc[2] == RTI_BC_OPEN_DEV) : (d.bc[3] == RTI_BC_OPEN_DEV);
+                const double mrad = radiate(d.g, eps, west ? p.H : p.HL, west ? p.e1 : p.e1L, west ? -1.0 : 1.0);
+                const double nrad = radiate(d.g, eps, south ? p.H : pp.H, south ? p.e1 : pp.e1, south ? -1.0 : 1.0);
+                if (xf_here && !col_xint) Mnew = (F)(xopen ? mrad : 0.0);
+                if (col_cell && !(rr >= 1 && rr <= ny - 1)) Nnew = (F)(yopen ? nrad : 0.0);
             }
             if (out_lane) {
                 const bool wx = xf_here && (col_xint || root), wy = col_cell && (yf_int || root);

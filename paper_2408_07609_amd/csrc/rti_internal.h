@@ -57,6 +57,9 @@ __host__ __device__ inline int tile_y(int tl, int tiles_x, int tiles_y)
     return RTI_TILE_ORDER ? tl % tiles_y : tl / tiles_x;
 }
 
+// Root side kinds of DomainDev::bc (the values of RTI_BC_OPEN / RTI_BC_WALL).
+#define RTI_BC_OPEN_DEV 0
+
 // Static per-tile bits (host-computed whenever the tile grid is laid out).
 #define TI_PINNED 0x1u      // never skipped and never reported stationary
 #define TI_CHILD 0x2u       // the tile's extended region meets a child's ring or edge faces
