@@ -253,8 +253,10 @@ int rti_domain_tile_rows(const rti_domain *dom, int32_t *rows);
 /* Autotuner of the tile shape: for each candidate height (4, 5, 6, 8, 10, 12,
  * 16, 24), run 2 untimed steps and then nsteps timed steps from the domain's
  * current state with every tile computed (so the choice does not depend on how
- * much of the state is stationary at the time), keep the fastest height, and
- * restore the state, the maxima and the step count exactly as they were.
+ * much of the state is stationary at the time), keep the shortest height whose
+ * time is within 2 % of the fastest (runs skip stationary tiles, at a finer
+ * grain with shorter tiles), and restore the state, the maxima and the step
+ * count exactly as they were.
  * nsteps >= 1.  *rows_out (may be NULL) receives the height chosen; ms_out
  * (may be NULL) the average time [ms] of a step computing every tile at that
  * height.  Allocates a device snapshot of the state for the

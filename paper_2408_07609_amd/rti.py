@@ -545,16 +545,19 @@ def autotune_batch_rows(domains, nsteps=8, candidates=(6, 8, 10, 12, 16, 24)):
     steps with every tile computed (rti_batch_profile), and keep the fastest.
     A member's own autotuner picks short tiles for a small domain alone (more
     wavefronts for it), but in a batch the members' tiles already fill the
-    GPU, and short tiles only add recomputed warm-up rows.  The trials step
-    the domains: pass copies made for tuning (same shapes), not the domains
-    to be run.  Returns (rows, fused-kernel ms per step at that height)."""
-    best = None
+    GPU, and short tiles only add recomputed warm-up rows.  Of the heights
+    within 2 % of the fastest the shortest is kept: a run skips stationary
+    tiles, at a finer grain with shorter tiles, which the every-tile trials
+    do not see.  The trials step the domains: pass copies made for tuning
+    (same shapes), not the domains to be run.  Returns (rows, fused-kernel ms
+    per step at that height)."""
+    times = []
     for rows in candidates:
         for d in domains:
             d.set_tile_rows(rows)
         with Batch(domains, flags=RTI_FLAG_NO_ACTIVE) as b:
             b.step(2)
             fused_ms, _, _ = b.profile(nsteps)
-        if best is None or fused_ms < best[1]:
-            best = (rows, fused_ms)
-    return best
+        times.append((rows, fused_ms))
+    fastest = min(ms for _, ms in times)
+    return min((r, ms) for r, ms in times if ms <= fastest * 1.02)
