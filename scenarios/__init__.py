@@ -400,6 +400,18 @@ def _touching_chain(sc: Scenario, coast, specs):
         sc.levels.append(union_level(p, rects))
 
 
+def c3_touching_nearshore(seed: int = 3) -> Scenario:
+    """The touching-block C3 layout with its uplift moved 10 km offshore, as
+    in c3_nearshore, so that the 30 m and 10 m bands flood within the first
+    600 s: the full-size wet/dry reference window of levels of touching
+    blocks."""
+    sc = c3_touching(seed=seed)
+    src = sc.source
+    sc.name = "c3-touching-nearshore"
+    sc.source = Source(src.xc + 140e3, src.yc, src.a, src.b, src.theta, src.amp, src.shape)
+    return sc
+
+
 def small_touching(seed: int = 29) -> Scenario:
     """A small chain of levels of touching blocks over a seeded coast: a
     90x72 root at 810 m; at 270 m two blocks of 12x8 root cells, one above

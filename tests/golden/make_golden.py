@@ -10,6 +10,11 @@ SHA-256 of the oracle source that wrote it.
 
     python tests/golden/make_golden.py c2    # configuration 2, all 18,000 steps (about 1.5 h on 8 cores)
     python tests/golden/make_golden.py c3w   # configuration 3's grid, near-shore source, 3000 steps (about 1 h)
+    python tests/golden/make_golden.py c3tw  # the same as touching blocks (masked levels), 3000 steps (about 1.5 h)
+
+On a masked level (touching blocks) the ring cells and the injected faces
+are those of the covered region (oracle.coverage), and cells outside are
+not sampled.
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ CASES = {
     # name: (scenario, steps (None: the configuration's whole run), file)
     "c2": (lambda: scenarios.c2(), None, "c2_full_run.npz"),
     "c3w": (lambda: scenarios.c3_nearshore(), 3000, "c3_nearshore_3000.npz"),
+    "c3tw": (lambda: scenarios.c3_touching_nearshore(), 3000, "c3_touching_nearshore_3000.npz"),
 }
 RANDOM = 4096
 SHORE_CAP = 8192
@@ -46,17 +52,35 @@ def sha(a):
 
 
 def ring_cells(sc, k):
-    """(i, j) of level k's cells on the ring of every child's footprint."""
+    """(i, j) of level k's cells on the ring of every child's footprint: the
+    covered parent cells with an uncovered one among their 8 neighbours (a
+    rectangle's outermost ring)."""
     out = []
     for c, lv in enumerate(sc.levels):
         if lv["parent"] != k:
             continue
-        fw, fh = lv["nx"] // 3, lv["ny"] // 3
+        cov = np.pad(oracle.coverage(lv), 1)
+        fh, fw = cov.shape[0] - 2, cov.shape[1] - 2
         for J in range(fh):
             for I in range(fw):
-                if I in (0, fw - 1) or J in (0, fh - 1):
+                if cov[J + 1, I + 1] and not cov[J:J + 3, I:I + 3].all():
                     out.append((lv["off_i"] + I, lv["off_j"] + J))
     return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
+def injected_faces(lv):
+    """Flat indices into M (ny x nx+1) and N (ny+1 x nx) of a child's faces that
+    its parent injects: those on a parent face between a covered and an
+    uncovered parent cell (a rectangle's four edges)."""
+    ny, nx = lv["ny"], lv["nx"]
+    cov = np.pad(oracle.coverage(lv), 1)
+    xs = cov[1:-1, :-1] != cov[1:-1, 1:]            # (fh, fw + 1): x-face I between parent cells I-1, I
+    ys = cov[:-1, 1:-1] != cov[1:, 1:-1]            # (fh + 1, fw)
+    J, I = np.nonzero(xs)
+    mx = ((3 * J)[:, None] + np.arange(3)) * (nx + 1) + (3 * I)[:, None]
+    J, I = np.nonzero(ys)
+    ny_ = (3 * J)[:, None] * nx + (3 * I)[:, None] + np.arange(3)
+    return mx.ravel(), ny_.ravel()
 
 
 def shoreline_band(h, e, eps, rng):
@@ -97,19 +121,17 @@ def main(name):
         ny, nx = e.shape
         out[f"l{k}_sha"] = np.array([sha(e), sha(M), sha(N), sha(z)])
         rc = ring_cells(sc, k)
+        inside = oracle.level_mask(lv).ravel()
         cells = np.concatenate([rc[:, 1] * nx + rc[:, 0],
                                 shoreline_band(h, e, sc.dry_eps, rng),
-                                rng.choice(nx * ny, size=min(RANDOM, nx * ny), replace=False)])
+                                rng.choice(np.flatnonzero(inside), size=min(RANDOM, int(inside.sum())), replace=False)])
         cells = np.unique(cells)
         j, i = np.divmod(cells, nx)
         out[f"l{k}_cell"] = cells
         out[f"l{k}_eta"], out[f"l{k}_zmax"] = e[j, i], z[j, i]
         # faces: a child's edge faces (those the parent injects) and random interior faces
         if lv["parent"] >= 0:
-            jm = np.arange(ny)
-            mx = np.concatenate([jm * (nx + 1), jm * (nx + 1) + nx])
-            iN = np.arange(nx)
-            ny_ = np.concatenate([iN, ny * nx + iN])
+            mx, ny_ = injected_faces(lv)
         else:
             mx, ny_ = np.zeros(0, np.int64), np.zeros(0, np.int64)
         mx = np.unique(np.concatenate([mx, rng.choice(M.size, size=RANDOM, replace=False)]))
