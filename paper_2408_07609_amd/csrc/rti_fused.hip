@@ -251,16 +251,15 @@ __device__ void inject_edges(const DomainDev &d, const LevelDev &L, int b, int c
 // and the nest exchanges of Sec. IV-C for those rows' cells and faces).
 // Returns whether every value written was left bitwise unchanged (the
 // wavefront's part of the tile's stationarity); the caller records the flag.
-template <typename F>
-__device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int l, int r0, int r1)
+template <typename F, bool Ring>
+__device__ __forceinline__ bool fused_rows_k(const DomainDev &d, int b, int g, int l, int r0, int r1)
 {
     const LevelDev &L = level_of(d, l);
     const int tl = g - L.tile_base;
     const int x0 = tile_x(tl, L.tiles_x, L.tiles_y) * RTI_TW;
     const int y0 = tile_y(tl, L.tiles_x, L.tiles_y) * d.th + r0;     // first output row
     const int yend = y0 + (r1 - r0);                                 // one past the last
-    const uint8_t info = d.tinfo[g];
-    const bool has_child = (info & TI_CHILD) != 0;
+    constexpr bool has_child = Ring;                 // the tile meets a child's ring or edge faces
     const bool root = (l == 0);
     const unsigned cmask = has_child ? d.tcmask[g] : 0u;   // children whose edges the tile injects
 
@@ -303,11 +302,11 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
     auto ld_xf = [&](int row) -> F { return *reinterpret_cast<const F *>(Mb_a + ofs(row) * (uint32_t)sizeof(F)); };
     auto ld_yf = [&](int row) -> F { return *reinterpret_cast<const F *>(Nb_a + ofs(row) * (uint32_t)sizeof(F)); };
     // Ring means of the step (precomputed in the active-list launch), read like
-    // eta; a tile that meets no child ring reads eta again instead (a cache
-    // hit; the value is not used), so the load needs no branch.
+    // eta by the tiles that meet a child's ring; the others do not load them.
     const char *Rg_a = reinterpret_cast<const char *>((has_child ? L.ring : Eb) - pad);
     auto ld_ring = [&](int row) -> double {
-        return *reinterpret_cast<const double *>(Rg_a + ofs(row) * (uint32_t)sizeof(double));
+        if constexpr (Ring) return *reinterpret_cast<const double *>(Rg_a + ofs(row) * (uint32_t)sizeof(double));
+        else return 0.0;
     };
 
     const int t0 = y0 - 2;
@@ -370,7 +369,7 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
         double e1 = cur.E - r * (((double)cur.MxR - (double)cur.Mx) + ((double)cur.Ny - (double)p.Ny));
         e1 = (H_t + e1 < 0.0) ? -H_t : e1;
         e1 = (col_cell && row_cell) ? e1 : 0.0;
-        e1 = (has_child && col_cell && row_cell && cur.R == cur.R) ? cur.R : e1;
+        if constexpr (Ring) e1 = (col_cell && row_cell && cur.R == cur.R) ? cur.R : e1;
         cur.e1 = e1;
         // a water level this tile writes (row t is written in the next iteration) left unchanged?
         if (out_lane && col_cell && t >= y0 && t < yend && t < ny) quiet = quiet && same_bits(e1, cur.E);
@@ -433,7 +432,7 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
                 // the fluxes this tile writes left unchanged?
                 quiet = quiet && (!wx || same_bits(Mnew, xp.f)) && (!wy || same_bits(Nnew, yp.f));
                 bad = bad || (wx && !isfinite(Mnew)) || (wy && !isfinite(Nnew)) || (col_cell && rr < ny && !isfinite(p.e1));
-                if (has_child) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew, cmask);
+                if constexpr (Ring) inject_edges<F>(d, L, b, c, rr, xf_here && col_xint, yf_int, Mnew, Nnew, cmask);
             }
         }
     };
@@ -473,6 +472,16 @@ __device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int
 
     if (__any(bad ? 1 : 0) && lane == 0) atomicOr(&d.status[0], 1);   // sticky: RTI_EDIVERGED on the host
     return __all(quiet ? 1 : 0);
+}
+
+// Rows [r0, r1) of tile g (fused_rows_k), with or without the child-ring
+// path: a tile's static bits say whether it meets a child's ring or edge
+// faces; the others neither load ring means nor inject (wavefront-uniform).
+template <typename F>
+__device__ __forceinline__ bool fused_rows(const DomainDev &d, int b, int g, int l, int r0, int r1)
+{
+    if (d.tinfo[g] & TI_CHILD) return fused_rows_k<F, true>(d, b, g, l, r0, r1);
+    return fused_rows_k<F, false>(d, b, g, l, r0, r1);
 }
 
 // Stationarity history of tile g: bit1 <- bit0, bit0 <- this step left every
