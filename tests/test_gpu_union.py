@@ -87,13 +87,15 @@ def test_union_source_run():
 
 def test_touching_chain_source_run():
     """Levels of touching blocks inside levels of touching blocks (a 3 x 2
-    grid of 90 m blocks in two stepped 270 m blocks): 600 steps bitwise the
-    oracle; every level floods."""
+    grid of 90 m blocks in two stepped 270 m blocks): bitwise the oracle
+    after 600 steps and after 3000 (the flood running up and draining back
+    across the blocks' shared edges); every level floods."""
     sc = scenarios.small_touching()
     d, o = from_source(sc)
-    d.step(600)
-    o.step(600)
-    compare(d, o, len(sc.levels), "touching chain, 600 steps")
+    for n in (600, 2400):
+        d.step(n)
+        o.step(n)
+        compare(d, o, len(sc.levels), f"touching chain, {o.steps} steps")
     for k in (1, 2):
         land = (sc.levels[k]["h"] <= 0) & (sc.levels[k]["mask"] != 0)
         assert (o.max_inundation(k)[land] > 0.05).sum() > 10, f"level {k} does not flood"
