@@ -70,12 +70,16 @@ def measured_traffic(kernel, workload, cells_per_launch, tile_rows=None):
         return None
     with open(path) as f:
         t = json.load(f)
-    e = t.get(kernel)
-    if not e or e.get("source_hash") != source_hash() or e.get("workload") != workload:
-        return None
-    if tile_rows is not None and e.get("tile_rows") not in (None, tile_rows):
-        return None
-    return e["bytes_per_cell"] * cells_per_launch
+    # One entry per kernel and tile height ("k_fused@12"); the plain kernel
+    # name holds the entry of one height, stated in its tile_rows.
+    keys = ([f"{kernel}@{tile_rows}"] if tile_rows is not None else []) + [kernel]
+    for e in (t.get(k) for k in keys):
+        if not e or e.get("source_hash") != source_hash() or e.get("workload") != workload:
+            continue
+        if tile_rows is not None and e.get("tile_rows") not in (None, tile_rows):
+            continue
+        return e["bytes_per_cell"] * cells_per_launch
+    return None
 
 
 COPY_PROBE_BYTES = 1 << 30

@@ -10,7 +10,7 @@ that factor and by the cells of the workload give its HBM bytes per computed
 cell, stored with the kernel source hash so bench.py can tell when they are
 stale.
 
-    python bench_traffic.py FETCH_CSV WRITE_CSV --cells N --workload NAME [--key k_fused_fp32bulk]
+    python bench_traffic.py FETCH_CSV WRITE_CSV --cells N --workload NAME [--tile-rows R] [--key k_fused_fp32bulk]
 """
 from __future__ import annotations
 
@@ -43,7 +43,8 @@ def main():
     ap.add_argument("--cells", type=int, required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--kernel", default="k_fused", help="substring of the kernel name")
-    ap.add_argument("--key", default=None, help="entry name in the json (default: --kernel)")
+    ap.add_argument("--key", default=None,
+                    help="entry name in the json (default: --kernel, or --kernel@ROWS with --tile-rows)")
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height of the counted runs")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
@@ -61,7 +62,8 @@ def main():
         if not ker:
             sys.exit(f"no {args.kernel} dispatch in {path}")
         per[which] = (sum(ker) / len(ker)) * 1024 / factors[which]
-    out[args.key or args.kernel] = {
+    key = args.key or (f"{args.kernel}@{args.tile_rows}" if args.tile_rows else args.kernel)
+    out[key] = {
         "bytes_per_cell": (per["fetch"] + per["write"]) / args.cells,
         "fetch_bytes_per_launch": per["fetch"],
         "write_bytes_per_launch": per["write"],

@@ -64,3 +64,9 @@ def test_traffic_summary(tmp_path):
     assert e["copy_factor_fetch"] == pytest.approx(1.25) and e["copy_factor_write"] == pytest.approx(0.5)
     assert e["bytes_per_cell"] == pytest.approx((1000 * 1024 / 1.25 + 300 * 1024 / 0.5) / 1000)
     assert e["source_hash"] == source_hash()
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench_traffic.py"), str(tmp_path / "f.csv"),
+                        str(tmp_path / "w.csv"), "--cells", "1000", "--workload", "w", "--tile-rows", "12",
+                        "--out", str(out)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    t = json.loads(out.read_text())
+    assert set(t) == {"k_fused", "k_fused@12"} and t["k_fused@12"]["tile_rows"] == 12
