@@ -175,7 +175,12 @@ int rti_set_eta(rti_domain *dom, int32_t level, const double *eta0);
  * or wall sides of the root, and the output maxima; every level advances by
  * the same dt (Sec. V-A).  FP64 results are bitwise reproducible (every
  * operation correctly rounded).  nsteps >= 0.  RTI_EDIVERGED if an earlier
- * synchronising call found the domain diverged. */
+ * synchronising call found the domain diverged.
+ * Whole groups of 20 steps replay a HIP graph (unless RTI_FLAG_NO_GRAPH).
+ * After each graph the active-tile count of its last step is copied, on the
+ * stream, into pinned host memory the domain holds; when it is small the next
+ * graph launches the fused kernel on a small grid instead of one workgroup
+ * per tile (the same results either way). */
 int rti_step(rti_domain *dom, int64_t nsteps);
 
 /* Step until round(t_end / dt) steps have been taken in total (the paper's

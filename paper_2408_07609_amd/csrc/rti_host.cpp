@@ -585,6 +585,7 @@ int check_level(const rti_domain *D, int level)
 int rti_rt::forget_quiet(rti_domain *D)
 {
     HIP_TRY(hipMemsetAsync(D->dev.tflag, 0, (size_t)D->plan.ntiles, D->stream));
+    if (D->hint) *D->hint = -1;          // every tile is listed next: no sparse graph
     return RTI_OK;
 }
 
@@ -676,7 +677,10 @@ int device_initial(rti_domain *D, int k, const rti_source *src)
 }
 
 // every_tile: compute every tile this step whatever the domain's flags.
-int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
+// small_grid: the fused kernel on the persistent grid (it loops over the
+// list, so any number of active tiles is computed, only more slowly than by
+// one workgroup per tile).
+int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, bool small_grid = false)
 {
     if (D->flags & RTI_FLAG_PHASED) {
         HIP_TRY(launch_mass(D->dev, b, s));
@@ -686,11 +690,26 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false)
     } else {
         const bool all = every_tile || (D->flags & RTI_FLAG_NO_ACTIVE);
         HIP_TRY(launch_active(D->dev, b, all ? 1 : 0, s));
-        HIP_TRY(launch_fused(D->dev, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s,
-                             all));
+        HIP_TRY(launch_fused(D->dev, b,
+                             fused_grid(D->dev.ntiles, small_grid || (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count),
+                             s, all));
     }
     HIP_TRY(launch_inject(D->dev, b, s));
     return RTI_OK;
+}
+
+// Graphs of sparse steps: when the last graph's last step listed at most half
+// the split kernel's share of tiles, the next graph's steps will most likely
+// all be split-kernel steps, and the fused kernel goes on the small grid
+// instead of dispatching one idle workgroup per tile.  The count is a hint
+// only (read without synchronising, possibly one graph old): a wrong choice
+// costs time, never results.
+bool sparse_graph(const rti_domain *D)
+{
+    if (!D->hint || D->dev.split_max <= 0 || (D->flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_PERSISTENT))) return false;
+    if (fused_grid(D->dev.ntiles, true, D->cu_count) >= fused_grid(D->dev.ntiles, false, D->cu_count)) return false;
+    const int n = __atomic_load_n(D->hint, __ATOMIC_RELAXED);
+    return n >= 0 && n <= D->dev.split_max / 2;
 }
 
 // Cells inside the tiles of the current active list (synchronises).
@@ -759,8 +778,12 @@ void drop_graphs(rti_domain *D)
     for (int p = 0; p < 2; ++p) {
         if (D->exec[p]) (void)hipGraphExecDestroy(D->exec[p]);
         if (D->graph[p]) (void)hipGraphDestroy(D->graph[p]);
+        if (D->exec_small[p]) (void)hipGraphExecDestroy(D->exec_small[p]);
+        if (D->graph_small[p]) (void)hipGraphDestroy(D->graph_small[p]);
         D->exec[p] = nullptr;
         D->graph[p] = nullptr;
+        D->exec_small[p] = nullptr;
+        D->graph_small[p] = nullptr;
     }
 }
 
@@ -793,12 +816,13 @@ int retile(rti_domain *D, int th)
     return RTI_OK;
 }
 
-int build_graph(rti_domain *D, int parity)
+int build_graph(rti_domain *D, int parity, bool small_grid)
 {
     if (!D->capture) HIP_TRY(hipStreamCreateWithFlags(&D->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(D->capture, hipStreamCaptureModeThreadLocal));
     int rc = RTI_OK;
-    for (int k = 0; k < kGraphSteps && rc == RTI_OK; ++k) rc = launch_step(D, (parity + k) & 1, D->capture);
+    for (int k = 0; k < kGraphSteps && rc == RTI_OK; ++k)
+        rc = launch_step(D, (parity + k) & 1, D->capture, false, small_grid);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(D->capture, &g);
     if (rc != RTI_OK) {
@@ -812,8 +836,8 @@ int build_graph(rti_domain *D, int parity)
         (void)hipGraphDestroy(g);
         return fail(RTI_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
-    D->graph[parity] = g;
-    D->exec[parity] = x;
+    (small_grid ? D->graph_small : D->graph)[parity] = g;
+    (small_grid ? D->exec_small : D->exec)[parity] = x;
     return RTI_OK;
 }
 
@@ -914,10 +938,12 @@ int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_byt
         }
         e = hipEventCreate(&D->tev[0]);
         if (e == hipSuccess) e = hipEventCreate(&D->tev[1]);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&D->hint, sizeof(int), hipHostMallocDefault);
         if (e != hipSuccess) {
             rti_domain_destroy(D);
-            return fail(RTI_EHIP, "creating the timing events failed: %s", hipGetErrorString(e));
+            return fail(RTI_EHIP, "creating the timing events or the pinned hint failed: %s", hipGetErrorString(e));
         }
+        *D->hint = -1;                   // no hint until a graph has run
         if (arena) {
             D->mem = arena;
         } else {
@@ -1093,11 +1119,24 @@ int rti_step(rti_domain *D, int64_t nsteps)
         const bool graphs = !(D->flags & RTI_FLAG_NO_GRAPH);
         while (nsteps > 0) {
             if (graphs && nsteps >= kGraphSteps) {
-                if (!D->exec[D->cur]) {
-                    int rc = build_graph(D, D->cur);
+                const bool small = sparse_graph(D);
+                hipGraphExec_t &x = (small ? D->exec_small : D->exec)[D->cur];
+                if (!x) {
+                    int rc = build_graph(D, D->cur, small);
                     if (rc) return rc;
                 }
-                HIP_TRY(hipGraphLaunch(D->exec[D->cur], D->stream));
+                HIP_TRY(hipGraphLaunch(x, D->stream));
+                // the active tiles of the graph's last step (parity cur + kGraphSteps - 1), for the next
+                // choice: after every graph while the count is small or unknown, after every 16th once it
+                // is large (a run rarely falls back to sparse steps, and each copy is a few microseconds)
+                if (D->hint) {
+                    const int last = __atomic_load_n(D->hint, __ATOMIC_RELAXED);
+                    if (last < 0 || last <= 2 * D->dev.split_max || ++D->hint_age >= 16) {
+                        HIP_TRY(hipMemcpyAsync(D->hint, D->dev.count + ((D->cur + kGraphSteps - 1) & 1), sizeof(int),
+                                               hipMemcpyDeviceToHost, D->stream));
+                        D->hint_age = 0;
+                    }
+                }
                 D->steps += kGraphSteps;
                 D->own_steps += kGraphSteps;
                 nsteps -= kGraphSteps;
@@ -1570,6 +1609,7 @@ void rti_domain_destroy(rti_domain *D)
     if (D->capture) (void)hipStreamDestroy(D->capture);
     for (auto &x : D->tev)
         if (x) (void)hipEventDestroy(x);
+    if (D->hint) (void)hipHostFree(D->hint);
     if (D->owns_mem && D->mem) (void)hipFree(D->mem);
     delete D;
 }

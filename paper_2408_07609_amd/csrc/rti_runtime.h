@@ -95,6 +95,13 @@ struct rti_domain {
     hipStream_t capture = nullptr;       // private, for graph capture
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // The same steps with the fused kernel on a small grid (one that loops over
+    // the list), for runs of sparse steps: the full grid dispatches one
+    // workgroup per tile even when the split kernel does all the work.
+    hipGraph_t graph_small[2] = {nullptr, nullptr};
+    hipGraphExec_t exec_small[2] = {nullptr, nullptr};
+    int *hint = nullptr;                 // pinned host memory: the active tiles of the last graph's last step
+    int hint_age = 0;                    // graphs since the hint was last refreshed
     hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of the autotuner, made at create
     void *mem = nullptr;                 // base of the carved memory
     bool owns_mem = false;

@@ -84,6 +84,49 @@ def test_c3_full_size_steps():
 
 
 @pytest.mark.timeout(900)
+def test_c2_small_grid_is_exact():
+    """The fused kernel on the small grid that loops over the active list
+    (what the graphs of sparse steps launch, and what RTI_FLAG_PERSISTENT
+    asks for) computes, bit for bit, what one workgroup per tile computes:
+    configuration 2 (14,000 tiles, more than the small grid's workgroups)
+    from its source for 300 steps, and 40 steps with every tile computed."""
+    from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PERSISTENT
+    sc = scenarios.c2()
+    for base, steps in ((0, 300), (RTI_FLAG_NO_ACTIVE, 40)):
+        a, b = gpu_domain(sc, flags=base), gpu_domain(sc, flags=base | RTI_FLAG_PERSISTENT)
+        for d in (a, b):
+            d.set_source(*sc.source.astuple())
+            d.step(steps)
+            d.sync()
+        for k in range(len(sc.levels)):
+            for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
+                assert np.array_equal(x, y), f"flags {base}: level {k}"
+        print(f"flags {base}: {steps} steps bitwise equal", flush=True)
+        a.close()
+        b.close()
+
+
+@pytest.mark.timeout(900)
+def test_c2_graphs_of_sparse_steps_are_exact():
+    """Configuration 2 from its source for 1000 steps: the graph-replayed run
+    (graphs of sparse steps on the small grid while few tiles are active,
+    the full grid after) equals, bit for bit, the same steps launched one by
+    one on the full grid."""
+    from paper_2408_07609_amd import RTI_FLAG_NO_GRAPH
+    sc = scenarios.c2()
+    a, b = gpu_domain(sc), gpu_domain(sc, flags=RTI_FLAG_NO_GRAPH)
+    for d in (a, b):
+        d.set_source(*sc.source.astuple())
+        d.step(1000)
+        d.sync()
+    for k in range(len(sc.levels)):
+        for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
+            assert np.array_equal(x, y), f"level {k}"
+    a.close()
+    b.close()
+
+
+@pytest.mark.timeout(900)
 def test_c2_tile_skipping_is_exact():
     """Configuration 2 from its source for 600 steps: the run that skips
     stationary tiles (dry land, sea still at rest) equals, bit for bit, the run that computes every tile,
