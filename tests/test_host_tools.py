@@ -70,3 +70,34 @@ def test_traffic_summary(tmp_path):
     assert r.returncode == 0, r.stderr
     t = json.loads(out.read_text())
     assert set(t) == {"k_fused", "k_fused@12"} and t["k_fused@12"]["tile_rows"] == 12
+
+
+def test_step_times_from_a_trace(tmp_path):
+    """bench_steps.py groups dispatches into steps at each k_active, starts the
+    run after the reset gap and averages each kernel over a window."""
+    import sqlite3
+    sys.path.insert(0, ROOT)
+    import bench_steps
+    db = tmp_path / "run_results.db"
+    c = sqlite3.connect(db)
+    c.execute("create table kernels (name text, start integer, duration integer)")
+    t = 0
+    rows = []
+    for s in range(400):
+        if s == 40:
+            t += 10_000_000                      # the reset to t = 0 before the timed run
+        small = 40 <= s < 140
+        for name, dur in (("k_active<double>", 5000), ("k_fused_loop<double>" if small else "k_fused<double>", 7000),
+                          ("k_fused_split<double>", 3000)):
+            rows.append((f"(anonymous namespace)::{name}(DomainDev, int)", t, dur))
+            t += dur
+        t += 1000
+    rows.insert(0, ("__amd_rocclr_copyBuffer", 0, 100))
+    c.executemany("insert into kernels values (?, ?, ?)", rows)
+    c.commit()
+    steps = bench_steps.steps_of(str(db))
+    assert len(steps) == 360
+    av, tot, period, nsmall = bench_steps.window(steps, 0, 200)
+    assert av["active"] == pytest.approx(5.0) and av["split"] == pytest.approx(3.0)
+    assert av["loop"] == pytest.approx(3.5) and av["fused"] == pytest.approx(3.5) and nsmall == 100
+    assert tot == pytest.approx(15.0) and period == pytest.approx(16.0)
