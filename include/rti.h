@@ -178,9 +178,11 @@ int rti_set_eta(rti_domain *dom, int32_t level, const double *eta0);
  * synchronising call found the domain diverged.
  * Whole groups of 20 steps replay a HIP graph (unless RTI_FLAG_NO_GRAPH).
  * After each graph the active-tile count of its last step is copied, on the
- * stream, into pinned host memory the domain holds; when it is small the next
- * graph launches the fused kernel on a small grid instead of one workgroup
- * per tile (the same results either way). */
+ * stream, into pinned host memory the domain holds; from it the next graph
+ * launches the fused kernel on a small looping grid (few active tiles), or
+ * leaves the sparse-step kernel out (many), or launches both as an eager
+ * step does; every kind computes every listed tile, so the results are the
+ * same either way. */
 int rti_step(rti_domain *dom, int64_t nsteps);
 
 /* Step until round(t_end / dt) steps have been taken in total (the paper's

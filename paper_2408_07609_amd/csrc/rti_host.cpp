@@ -677,10 +677,8 @@ int device_initial(rti_domain *D, int k, const rti_source *src)
 }
 
 // every_tile: compute every tile this step whatever the domain's flags.
-// small_grid: the fused kernel on the persistent grid (it loops over the
-// list, so any number of active tiles is computed, only more slowly than by
-// one workgroup per tile).
-int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, bool small_grid = false)
+// kind: kGraphDefault, or one of the graph kinds below (graphs only).
+int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, int kind = kGraphDefault)
 {
     if (D->flags & RTI_FLAG_PHASED) {
         HIP_TRY(launch_mass(D->dev, b, s));
@@ -690,26 +688,36 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, bo
     } else {
         const bool all = every_tile || (D->flags & RTI_FLAG_NO_ACTIVE);
         HIP_TRY(launch_active(D->dev, b, all ? 1 : 0, s));
-        HIP_TRY(launch_fused(D->dev, b,
-                             fused_grid(D->dev.ntiles, small_grid || (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count),
-                             s, all));
+        // kGraphDense: the fused kernel is told there is no split kernel (split_max 0 in its copy of
+        // the descriptor), so it computes every listed tile, however few, and no split launch follows
+        DomainDev dv = D->dev;
+        if (kind == kGraphDense) dv.split_max = 0;
+        const bool small = kind == kGraphSparse || (D->flags & RTI_FLAG_PERSISTENT) != 0;
+        HIP_TRY(launch_fused(dv, b, fused_grid(D->dev.ntiles, small, D->cu_count), s, all));
     }
     HIP_TRY(launch_inject(D->dev, b, s));
     return RTI_OK;
 }
 
-// Graphs of sparse steps: when the last graph's last step listed at most half
-// the split kernel's share of tiles, the next graph's steps will most likely
-// all be split-kernel steps, and the fused kernel goes on the small grid
-// instead of dispatching one idle workgroup per tile.  The count is a hint
-// only (read without synchronising, possibly one graph old): a wrong choice
-// costs time, never results.
-bool sparse_graph(const rti_domain *D)
+// The kind of the next graph, from the active tiles of the last graph's last
+// step.  At most half the split kernel's share of tiles: the coming steps
+// will most likely all be split-kernel steps, so the fused kernel goes on the
+// small grid instead of dispatching one idle workgroup per tile
+// (kGraphSparse).  More than twice that share: they will most likely all be
+// fused-kernel steps, so the split kernel, which would return at once, is
+// left out (kGraphDense).  Otherwise, or with no count yet, both kernels as in
+// an eager step.  The count is a hint only (read without synchronising,
+// possibly some graphs old): every kind computes every listed tile, so a
+// wrong choice costs time, never results.
+int graph_kind(const rti_domain *D)
 {
-    if (!D->hint || D->dev.split_max <= 0 || (D->flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_PERSISTENT))) return false;
-    if (fused_grid(D->dev.ntiles, true, D->cu_count) >= fused_grid(D->dev.ntiles, false, D->cu_count)) return false;
+    if (!D->hint || D->dev.split_max <= 0 || (D->flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_PERSISTENT)))
+        return kGraphDefault;
     const int n = __atomic_load_n(D->hint, __ATOMIC_RELAXED);
-    return n >= 0 && n <= D->dev.split_max / 2;
+    if (n < 0) return kGraphDefault;
+    if (n > 2 * D->dev.split_max) return kGraphDense;
+    const bool smaller = fused_grid(D->dev.ntiles, true, D->cu_count) < fused_grid(D->dev.ntiles, false, D->cu_count);
+    return (smaller && n <= D->dev.split_max / 2) ? kGraphSparse : kGraphDefault;
 }
 
 // Cells inside the tiles of the current active list (synchronises).
@@ -776,14 +784,12 @@ int upload_tiles(rti_domain *D)
 void drop_graphs(rti_domain *D)
 {
     for (int p = 0; p < 2; ++p) {
-        if (D->exec[p]) (void)hipGraphExecDestroy(D->exec[p]);
-        if (D->graph[p]) (void)hipGraphDestroy(D->graph[p]);
-        if (D->exec_small[p]) (void)hipGraphExecDestroy(D->exec_small[p]);
-        if (D->graph_small[p]) (void)hipGraphDestroy(D->graph_small[p]);
-        D->exec[p] = nullptr;
-        D->graph[p] = nullptr;
-        D->exec_small[p] = nullptr;
-        D->graph_small[p] = nullptr;
+        for (int k = 0; k < kGraphKinds; ++k) {
+            if (D->exec[k][p]) (void)hipGraphExecDestroy(D->exec[k][p]);
+            if (D->graph[k][p]) (void)hipGraphDestroy(D->graph[k][p]);
+            D->exec[k][p] = nullptr;
+            D->graph[k][p] = nullptr;
+        }
     }
 }
 
@@ -816,13 +822,13 @@ int retile(rti_domain *D, int th)
     return RTI_OK;
 }
 
-int build_graph(rti_domain *D, int parity, bool small_grid)
+int build_graph(rti_domain *D, int parity, int kind)
 {
     if (!D->capture) HIP_TRY(hipStreamCreateWithFlags(&D->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(D->capture, hipStreamCaptureModeThreadLocal));
     int rc = RTI_OK;
     for (int k = 0; k < kGraphSteps && rc == RTI_OK; ++k)
-        rc = launch_step(D, (parity + k) & 1, D->capture, false, small_grid);
+        rc = launch_step(D, (parity + k) & 1, D->capture, false, kind);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(D->capture, &g);
     if (rc != RTI_OK) {
@@ -836,8 +842,8 @@ int build_graph(rti_domain *D, int parity, bool small_grid)
         (void)hipGraphDestroy(g);
         return fail(RTI_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
-    (small_grid ? D->graph_small : D->graph)[parity] = g;
-    (small_grid ? D->exec_small : D->exec)[parity] = x;
+    D->graph[kind][parity] = g;
+    D->exec[kind][parity] = x;
     return RTI_OK;
 }
 
@@ -1119,10 +1125,10 @@ int rti_step(rti_domain *D, int64_t nsteps)
         const bool graphs = !(D->flags & RTI_FLAG_NO_GRAPH);
         while (nsteps > 0) {
             if (graphs && nsteps >= kGraphSteps) {
-                const bool small = sparse_graph(D);
-                hipGraphExec_t &x = (small ? D->exec_small : D->exec)[D->cur];
+                const int kind = graph_kind(D);
+                hipGraphExec_t &x = D->exec[kind][D->cur];
                 if (!x) {
-                    int rc = build_graph(D, D->cur, small);
+                    int rc = build_graph(D, D->cur, kind);
                     if (rc) return rc;
                 }
                 HIP_TRY(hipGraphLaunch(x, D->stream));

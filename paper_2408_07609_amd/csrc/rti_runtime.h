@@ -25,6 +25,11 @@ int fail(int code, const char *fmt, ...);
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 20;   // steps per captured graph (even: parity returns)
+// Kinds of step graphs: both fused and split launches, as an eager step
+// (default); the fused kernel on the small looping grid (runs of sparse
+// steps); the fused kernel alone, computing every listed tile (runs of dense
+// steps).
+enum { kGraphDefault = 0, kGraphSparse = 1, kGraphDense = 2, kGraphKinds = 3 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -93,13 +98,10 @@ struct rti_domain {
     hipStream_t stream = nullptr;        // borrowed (the batch's stream while in a batch)
     hipStream_t home_stream = nullptr;   // the stream given at create, restored on leaving a batch
     hipStream_t capture = nullptr;       // private, for graph capture
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    // The same steps with the fused kernel on a small grid (one that loops over
-    // the list), for runs of sparse steps: the full grid dispatches one
-    // workgroup per tile even when the split kernel does all the work.
-    hipGraph_t graph_small[2] = {nullptr, nullptr};
-    hipGraphExec_t exec_small[2] = {nullptr, nullptr};
+    // Step graphs per kind (rti_rt::kGraph*) and starting parity: the same
+    // steps with the fused and split launches shaped for the coming steps.
+    hipGraph_t graph[rti_rt::kGraphKinds][2] = {};
+    hipGraphExec_t exec[rti_rt::kGraphKinds][2] = {};
     int *hint = nullptr;                 // pinned host memory: the active tiles of the last graph's last step
     int hint_age = 0;                    // graphs since the hint was last refreshed
     hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of the autotuner, made at create
