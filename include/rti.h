@@ -261,7 +261,7 @@ int rti_domain_tile_rows(const rti_domain *dom, int32_t *rows);
  * 16, 24), run 2 untimed steps and then nsteps timed steps from the domain's
  * current state with every tile computed (so the choice does not depend on how
  * much of the state is stationary at the time), keep the shortest height whose
- * time is within 2 % of the fastest (runs skip stationary tiles, at a finer
+ * time is within 1 % of the fastest (runs skip stationary tiles, at a finer
  * grain with shorter tiles), and restore the state, the maxima and the step
  * count exactly as they were.
  * nsteps >= 1.  *rows_out (may be NULL) receives the height chosen; ms_out
