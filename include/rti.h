@@ -149,6 +149,9 @@ int rti_domain_footprint(const rti_domain_desc *desc, size_t *bytes);
  * is NULL, copy the bathymetry, and set the lake at rest (eta = 0 at sea,
  * -h on land, no flux).  hip_stream (a hipStream_t, may be NULL for the
  * default stream) is borrowed: every kernel of this domain runs on it.
+ * Besides the device memory, the domain holds two timing events and one
+ * word of pinned host memory (the active-tile count rti_step reads back),
+ * released by rti_domain_destroy.
  * Validation happens before any HIP call, so it works without a GPU. */
 int rti_domain_create(const rti_domain_desc *desc, void *arena, size_t arena_bytes,
                       void *hip_stream, rti_domain **out);
