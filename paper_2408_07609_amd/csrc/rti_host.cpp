@@ -677,7 +677,8 @@ int device_initial(rti_domain *D, int k, const rti_source *src)
 }
 
 // every_tile: compute every tile this step whatever the domain's flags.
-// kind: kGraphDefault, or one of the graph kinds below (graphs only).
+// kind: the step-graph kind (kGraph*, rti_runtime.h) being captured; eager
+// steps are kGraphDefault.
 int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, int kind = kGraphDefault)
 {
     if (D->flags & RTI_FLAG_PHASED) {
