@@ -181,11 +181,10 @@ int rti_set_eta(rti_domain *dom, int32_t level, const double *eta0);
  * synchronising call found the domain diverged.
  * Whole groups of 20 steps replay a HIP graph (unless RTI_FLAG_NO_GRAPH).
  * After each graph the active-tile count of its last step is copied, on the
- * stream, into pinned host memory the domain holds; from it the next graph
- * launches the fused kernel on a small looping grid (few active tiles), or
- * leaves the sparse-step kernel out (many), or launches both as an eager
- * step does; every kind computes every listed tile, so the results are the
- * same either way. */
+ * stream, into pinned host memory the domain holds; when it is large the
+ * next graph leaves the sparse-step kernel out (the fused kernel then
+ * computes every listed tile, however few), else it launches both as an
+ * eager step does; the results are the same either way. */
 int rti_step(rti_domain *dom, int64_t nsteps);
 
 /* Step until round(t_end / dt) steps have been taken in total (the paper's
@@ -247,6 +246,11 @@ int rti_active_tiles(rti_domain *dom, int64_t *active, int64_t *total, int64_t *
  * cell of every level at every step, *computed only the cells of the tiles
  * the fused kernel computed (stationary tiles skipped).  Synchronises. */
 int rti_cell_updates(rti_domain *dom, int64_t *all, int64_t *computed);
+
+/* Step graphs this domain has launched, per kind (see rti_step): counts[0]
+ * both kernels as an eager step, counts[1] the fused kernel alone (after
+ * many active tiles).  For observability; does not synchronise. */
+int rti_graph_launches(const rti_domain *dom, int64_t counts[2]);
 
 /* Tile shape of the fused kernel.  A tile is 60 columns wide and `rows` rows
  * high, rows in [RTI_TILE_ROWS_MIN, RTI_TILE_ROWS_MAX] (default

@@ -693,32 +693,31 @@ int launch_step(rti_domain *D, int b, hipStream_t s, bool every_tile = false, in
         // the descriptor), so it computes every listed tile, however few, and no split launch follows
         DomainDev dv = D->dev;
         if (kind == kGraphDense) dv.split_max = 0;
-        const bool small = kind == kGraphSparse || (D->flags & RTI_FLAG_PERSISTENT) != 0;
-        HIP_TRY(launch_fused(dv, b, fused_grid(D->dev.ntiles, small, D->cu_count), s, all));
+        HIP_TRY(launch_fused(dv, b, fused_grid(D->dev.ntiles, (D->flags & RTI_FLAG_PERSISTENT) != 0, D->cu_count), s,
+                             all));
     }
     HIP_TRY(launch_inject(D->dev, b, s));
     return RTI_OK;
 }
 
 // The kind of the next graph, from the active tiles of the last graph's last
-// step.  At most half the split kernel's share of tiles: the coming steps
-// will most likely all be split-kernel steps, so the fused kernel goes on the
-// small grid instead of dispatching one idle workgroup per tile
-// (kGraphSparse).  More than twice that share: they will most likely all be
-// fused-kernel steps, so the split kernel, which would return at once, is
-// left out (kGraphDense).  Otherwise, or with no count yet, both kernels as in
-// an eager step.  The count is a hint only (read without synchronising,
-// possibly some graphs old): every kind computes every listed tile, so a
-// wrong choice costs time, never results.
+// step: more than twice the split kernel's share of tiles, and the coming
+// steps will most likely all be fused-kernel steps, so the split kernel,
+// which would return at once, is left out (kGraphDense); otherwise, or with
+// no count yet, both kernels as in an eager step.  The count is a hint only:
+// it is read without synchronising and lags the graphs already enqueued (by
+// many graphs when the host runs ahead), and a fused kernel with no split
+// share computes every listed tile, so a stale count costs time, never
+// results.  (The active-tile count rarely falls during a forecast, so a
+// stale large count is rarely wrong.  A kind for sparse steps, the fused
+// kernel on the small looping grid, was dropped: the count grows, so a stale
+// small one put runs of dense steps on that grid.)
 int graph_kind(const rti_domain *D)
 {
     if (!D->hint || D->dev.split_max <= 0 || (D->flags & (RTI_FLAG_NO_ACTIVE | RTI_FLAG_PERSISTENT)))
         return kGraphDefault;
     const int n = __atomic_load_n(D->hint, __ATOMIC_RELAXED);
-    if (n < 0) return kGraphDefault;
-    if (n > 2 * D->dev.split_max) return kGraphDense;
-    const bool smaller = fused_grid(D->dev.ntiles, true, D->cu_count) < fused_grid(D->dev.ntiles, false, D->cu_count);
-    return (smaller && n <= D->dev.split_max / 2) ? kGraphSparse : kGraphDefault;
+    return n > 2 * D->dev.split_max ? kGraphDense : kGraphDefault;
 }
 
 // Cells inside the tiles of the current active list (synchronises).
@@ -1133,6 +1132,7 @@ int rti_step(rti_domain *D, int64_t nsteps)
                     if (rc) return rc;
                 }
                 HIP_TRY(hipGraphLaunch(x, D->stream));
+                D->graph_launches[kind] += 1;
                 // the active tiles of the graph's last step (parity cur + kGraphSteps - 1), for the next
                 // choice: after every graph while the count is small or unknown, after every 16th once it
                 // is large (a run rarely falls back to sparse steps, and each copy is a few microseconds)
@@ -1439,6 +1439,13 @@ int rti_domain_tile_rows(const rti_domain *D, int32_t *rows)
 {
     if (!D || !rows) return fail(RTI_EINVAL, "NULL argument");
     *rows = D->plan.th;
+    return RTI_OK;
+}
+
+int rti_graph_launches(const rti_domain *D, int64_t counts[2])
+{
+    if (!D || !counts) return fail(RTI_EINVAL, "NULL argument");
+    for (int k = 0; k < kGraphKinds; ++k) counts[k] = D->graph_launches[k];
     return RTI_OK;
 }
 

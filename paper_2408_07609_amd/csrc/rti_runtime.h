@@ -26,10 +26,9 @@ int fail(int code, const char *fmt, ...);
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 20;   // steps per captured graph (even: parity returns)
 // Kinds of step graphs: both fused and split launches, as an eager step
-// (default); the fused kernel on the small looping grid (runs of sparse
-// steps); the fused kernel alone, computing every listed tile (runs of dense
-// steps).
-enum { kGraphDefault = 0, kGraphSparse = 1, kGraphDense = 2, kGraphKinds = 3 };
+// (default); the fused kernel alone, computing every listed tile (runs of
+// dense steps).
+enum { kGraphDefault = 0, kGraphDense = 1, kGraphKinds = 2 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -104,6 +103,7 @@ struct rti_domain {
     hipGraphExec_t exec[rti_rt::kGraphKinds][2] = {};
     int *hint = nullptr;                 // pinned host memory: the active tiles of the last graph's last step
     int hint_age = 0;                    // graphs since the hint was last refreshed
+    int64_t graph_launches[rti_rt::kGraphKinds] = {};   // graphs launched per kind
     hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of the autotuner, made at create
     void *mem = nullptr;                 // base of the carved memory
     bool owns_mem = false;

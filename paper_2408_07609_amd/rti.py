@@ -81,6 +81,7 @@ FUNCTIONS = {
                                               ctypes.POINTER(ctypes.c_int64)]),
     "rti_domain_set_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rti_domain_tile_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "rti_graph_launches": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rti_domain_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dptr]),
     "rti_domain_autotune_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                                    _dptr]),
@@ -258,6 +259,13 @@ def rti_domain_tile_rows(dom: int) -> int:
     n = ctypes.c_int32(0)
     _check(LIB.rti_domain_tile_rows(dom, ctypes.byref(n)))
     return int(n.value)
+
+
+def rti_graph_launches(dom: int):
+    """Step graphs launched per kind: (default, dense)."""
+    c = (ctypes.c_int64 * 2)()
+    _check(LIB.rti_graph_launches(dom, c))
+    return tuple(int(v) for v in c)
 
 
 def rti_domain_autotune(dom: int, nsteps: int):
@@ -461,6 +469,10 @@ class Domain:
     def cell_updates(self):
         """(all, computed) cell-updates of this domain's own steps."""
         return rti_cell_updates(self._h)
+
+    def graph_launches(self):
+        """Step graphs launched per kind: (default, dense)."""
+        return rti_graph_launches(self._h)
 
     # -- tile shape
     @property

@@ -86,8 +86,8 @@ def test_c3_full_size_steps():
 @pytest.mark.timeout(900)
 def test_c2_small_grid_is_exact():
     """The fused kernel on the small grid that loops over the active list
-    (what the graphs of sparse steps launch, and what RTI_FLAG_PERSISTENT
-    asks for) computes, bit for bit, what one workgroup per tile computes:
+    (what RTI_FLAG_PERSISTENT asks for) computes, bit for bit, what one
+    workgroup per tile computes:
     configuration 2 (14,000 tiles, more than the small grid's workgroups)
     from its source for 300 steps, and 40 steps with every tile computed."""
     from paper_2408_07609_amd import RTI_FLAG_NO_ACTIVE, RTI_FLAG_PERSISTENT
@@ -107,18 +107,24 @@ def test_c2_small_grid_is_exact():
 
 
 @pytest.mark.timeout(900)
-def test_c2_graphs_of_sparse_steps_are_exact():
-    """Configuration 2 from its source for 1000 steps: the graph-replayed run
-    (graphs of sparse steps on the small grid while few tiles are active,
-    the full grid after) equals, bit for bit, the same steps launched one by
-    one on the full grid."""
+def test_c2_graph_kinds_are_exact():
+    """Configuration 2 from its source for 2000 steps, one graph at a time
+    (so each graph's kind follows the count of the one before): graphs of
+    both kinds (both kernels while few tiles are active, the fused kernel
+    alone once many are) give, bit for bit, the same steps as launched one by
+    one."""
     from paper_2408_07609_amd import RTI_FLAG_NO_GRAPH
     sc = scenarios.c2()
     a, b = gpu_domain(sc), gpu_domain(sc, flags=RTI_FLAG_NO_GRAPH)
     for d in (a, b):
         d.set_source(*sc.source.astuple())
-        d.step(1000)
-        d.sync()
+        for _ in range(100):
+            d.step(20)
+            d.sync()
+    kinds = a.graph_launches()
+    print(f"graphs launched (default, dense): {kinds}", flush=True)
+    assert sum(kinds) == 100 and all(n > 0 for n in kinds), kinds
+    assert b.graph_launches() == (0, 0)
     for k in range(len(sc.levels)):
         for x, y in zip(a.get_state(k) + (a.max_inundation(k),), b.get_state(k) + (b.max_inundation(k),)):
             assert np.array_equal(x, y), f"level {k}"
